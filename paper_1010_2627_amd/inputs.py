@@ -1,0 +1,215 @@
+"""Seeded synthetic inputs: tight-binding strips, on-site disorder, energy grids.
+
+This module only *builds* the Hamiltonian data of a two-lead strip (the input
+of the method); it contains none of the transport arithmetic (no self-energy,
+no Green function, no trace).  Both the GPU path and the CPU oracle take their
+inputs from here and from nowhere else.
+
+Model (tight-binding Hamiltonian of the paper's Eq. (1), section 2.3): every
+site carries ``norb`` internal degrees of freedom, the hopping between
+neighbouring sites is an ``norb x norb`` matrix and each site has an
+``norb x norb`` on-site matrix.  Hoppings use the paper's sign (+t, the
+``scalarM(1.)`` of its first example, section 2.2).
+
+Slicing.  A strip is a sequence of identical slices n = 1..L along the
+transport direction.  Inside a slice the W sites are numbered along the
+transverse direction and the slice-local index of orbital ``o`` of site ``s``
+is ``s * norb + o`` (so a slice has dimension M = W * norb).  A strip class is
+described by
+
+* ``H0``   [M, M]  clean intra-slice Hamiltonian (hoppings inside the slice and
+  any uniform on-site term such as a Zeeman field);
+* ``vcol`` [W]     for every site ``a`` of slice n the site of slice n-1 it is
+  bonded to, or -1 when it has no bond to the previous slice;
+* ``vblk`` [W, norb, norb] the hopping block H_{n,n-1}(a, vcol[a]).
+
+Each site has at most one bond to the previous slice in every lattice built
+here (square lattice, spinful square lattice, brick-wall honeycomb), so the
+inter-slice hopping V = H_{n,n-1} is a block-monomial matrix.  The leads are
+semi-infinite repetitions of the clean slice (H0, V) (section 5.3-B: a lead
+repeats its interface layer, and the lead-to-system hopping equals the
+intra-lead one).  The per-slice on-site blocks ``onsite`` [L, W, norb, norb]
+hold the disorder and are added to H0 on the system slices only.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SIGMA0 = np.eye(2, dtype=np.complex128)
+SIGMAX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+SIGMAY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+SIGMAZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+# Seed conventions for the synthetic workloads.
+SEED_BASE = 10102627        # realization r uses SEED_BASE + r
+SEED_UNEVEN_LAYOUT = 10102626  # draws (W, L, w) of the uneven batch
+SEED_UNEVEN_STRIP = SEED_BASE + 1000  # strip p of the uneven batch uses this + p
+
+
+@dataclass
+class Strip:
+    """Clean strip class: slice Hamiltonian H0 and inter-slice coupling V."""
+
+    name: str
+    W: int
+    norb: int
+    H0: np.ndarray            # [M, M] complex128
+    vcol: np.ndarray          # [W] int32
+    vblk: np.ndarray          # [W, norb, norb] complex128
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def M(self) -> int:
+        return self.W * self.norb
+
+    def V_dense(self) -> np.ndarray:
+        """Assemble V = H_{n,n-1} as a dense [M, M] matrix."""
+        M, no = self.M, self.norb
+        V = np.zeros((M, M), dtype=np.complex128)
+        for a in range(self.W):
+            c = int(self.vcol[a])
+            if c >= 0:
+                V[a * no:(a + 1) * no, c * no:(c + 1) * no] = self.vblk[a]
+        return V
+
+
+def _check(strip: Strip) -> Strip:
+    M = strip.M
+    assert strip.H0.shape == (M, M) and strip.H0.dtype == np.complex128
+    assert np.allclose(strip.H0, strip.H0.conj().T), "H0 must be Hermitian"
+    assert strip.vcol.shape == (strip.W,) and strip.vcol.dtype == np.int32
+    assert strip.vblk.shape == (strip.W, strip.norb, strip.norb)
+    used = strip.vcol[strip.vcol >= 0]
+    assert len(np.unique(used)) == len(used), "each site of slice n-1 bonds at most once"
+    return strip
+
+
+def square_strip(W: int, t: float = 1.0, onsite: float = 0.0) -> Strip:
+    """Scalar (norb=1) square-lattice strip of width W, nearest-neighbour hopping +t."""
+    H0 = np.zeros((W, W), dtype=np.complex128)
+    for y in range(W - 1):
+        H0[y + 1, y] = t
+        H0[y, y + 1] = t
+    H0 += onsite * np.eye(W)
+    vcol = np.arange(W, dtype=np.int32)
+    vblk = np.full((W, 1, 1), t, dtype=np.complex128)
+    return _check(Strip(f"square_W{W}", W, 1, H0, vcol, vblk, {"t": t}))
+
+
+def rashba_strip(W: int, t: float = 1.0, alpha: float = 0.2, ez: float = 0.1) -> Strip:
+    """Spinful (norb=2) square-lattice strip with lattice Rashba coupling and a Zeeman field.
+
+    Hopping block from site i to its neighbour i+x (along the strip, i.e. the
+    inter-slice V) is t*s0 + i*alpha*s_y; from i to i+y (inside a slice) it is
+    t*s0 - i*alpha*s_x.  The Zeeman term ez*s_z (out of plane) sits on every
+    site, leads included, so it is part of H0.
+    """
+    no = 2
+    M = W * no
+    hx = t * SIGMA0 + 1j * alpha * SIGMAY
+    hy = t * SIGMA0 - 1j * alpha * SIGMAX
+    H0 = np.zeros((M, M), dtype=np.complex128)
+    for y in range(W):
+        H0[y * no:(y + 1) * no, y * no:(y + 1) * no] = ez * SIGMAZ
+    for y in range(W - 1):
+        H0[(y + 1) * no:(y + 2) * no, y * no:(y + 1) * no] = hy
+        H0[y * no:(y + 1) * no, (y + 1) * no:(y + 2) * no] = hy.conj().T
+    vcol = np.arange(W, dtype=np.int32)
+    vblk = np.broadcast_to(hx, (W, no, no)).astype(np.complex128).copy()
+    return _check(Strip(f"rashba_W{W}", W, no, H0, vcol, vblk,
+                        {"t": t, "alpha": alpha, "ez": ez}))
+
+
+def zigzag_strip(Nz: int, t: float = 1.0) -> Strip:
+    """Honeycomb zigzag ribbon as a brick-wall lattice, slice = 2 columns x Nz rows.
+
+    Rows are the zigzag chains (they run along the strip); every site has a
+    bond to its left and right neighbour in its row, and the vertical bond
+    (x, y)-(x, y+1) exists iff x + y is even.  A slice holds columns x = 2n
+    (local column 0) and x = 2n + 1 (local column 1); the slice-local index of
+    (c, y) is c * Nz + y, so M = 2 Nz.  The inter-slice bonds join column 1 of
+    slice n-1 to column 0 of slice n, row by row: V has rank Nz (singular).
+    """
+    M = 2 * Nz
+    H0 = np.zeros((M, M), dtype=np.complex128)
+    for y in range(Nz):
+        a, b = y, Nz + y                   # (col0, y) -- (col1, y)
+        H0[a, b] = H0[b, a] = t
+    for c in range(2):
+        for y in range(Nz - 1):
+            if (c + y) % 2 == 0:
+                a, b = c * Nz + y, c * Nz + y + 1
+                H0[a, b] = H0[b, a] = t
+    vcol = np.full(M, -1, dtype=np.int32)
+    vcol[:Nz] = Nz + np.arange(Nz, dtype=np.int32)
+    vblk = np.zeros((M, 1, 1), dtype=np.complex128)
+    vblk[:Nz, 0, 0] = t
+    return _check(Strip(f"zigzag_Nz{Nz}", M, 1, H0, vcol, vblk, {"t": t}))
+
+
+def onsite_disorder(strip: Strip, L: int, w: float, seed: int) -> np.ndarray:
+    """On-site blocks [L, W, norb, norb]: eps * identity with eps ~ U[-w/2, w/2].
+
+    The scalar draw follows the paper's disorder recipe W*(random()-0.5)
+    (section 5.3-A, "Introducing disorder"), drawn slice by slice then site by
+    site from numpy's PCG64 generator (not bit-compatible with Python's
+    ``random``).  Spinful strips get spin-independent disorder eps * s0.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps = rng.uniform(-0.5 * w, 0.5 * w, size=(L, strip.W)) if w > 0 else np.zeros((L, strip.W))
+    out = np.zeros((L, strip.W, strip.norb, strip.norb), dtype=np.complex128)
+    for o in range(strip.norb):
+        out[:, :, o, o] = eps
+    return out
+
+
+def clean_onsite(strip: Strip, L: int) -> np.ndarray:
+    return np.zeros((L, strip.W, strip.norb, strip.norb), dtype=np.complex128)
+
+
+def midpoint_grid(a: float, b: float, n: int) -> np.ndarray:
+    """n energies uniform in the open interval (a, b): a + (b-a)(j+1/2)/n."""
+    j = np.arange(n, dtype=np.float64)
+    return a + (b - a) * (j + 0.5) / n
+
+
+@dataclass
+class UnevenLayout:
+    widths: np.ndarray   # [S] int
+    lengths: np.ndarray  # [S] int
+    ws: np.ndarray       # [S] disorder strengths
+    seeds: np.ndarray    # [S] per-strip disorder seed
+
+
+def uneven_layout(n_strips: int = 512, wmin: int = 32, wmax: int = 256, wstep: int = 32,
+                  lmin: int = 256, lmax: int = 2048, dmin: float = 0.5, dmax: float = 3.0,
+                  seed: int = SEED_UNEVEN_LAYOUT) -> UnevenLayout:
+    """Widths ~ U{wmin, wmin+wstep, .., wmax}, lengths ~ U[lmin, lmax], w ~ U[dmin, dmax]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    choices = np.arange(wmin, wmax + 1, wstep)
+    widths = rng.choice(choices, size=n_strips)
+    lengths = rng.integers(lmin, lmax + 1, size=n_strips)
+    ws = rng.uniform(dmin, dmax, size=n_strips)
+    seeds = SEED_UNEVEN_STRIP + np.arange(n_strips)
+    return UnevenLayout(widths.astype(np.int64), lengths.astype(np.int64), ws, seeds)
+
+
+def general_square_system(sites, t: float = 1.0):
+    """Dense Hamiltonian of an arbitrary set of square-lattice sites (scalar, on-site 0).
+
+    ``sites`` is a list of integer (x, y) pairs; two sites are bonded when
+    their distance is one lattice step.  Returns (H [N, N], index dict).
+    Used for the non-strip worked example of section 2.2.
+    """
+    index = {tuple(s): i for i, s in enumerate(sites)}
+    N = len(sites)
+    H = np.zeros((N, N), dtype=np.complex128)
+    for (x, y), i in index.items():
+        for dx, dy in ((1, 0), (0, 1)):
+            j = index.get((x + dx, y + dy))
+            if j is not None:
+                H[i, j] = H[j, i] = t
+    return H, index
