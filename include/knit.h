@@ -1,0 +1,222 @@
+/*
+ * knit.h -- C ABI of libknit: the two-lead strip transport path on MI355X (gfx950).
+ *
+ * What is computed (tight-binding model of Eq. (1), objects of section 2.3):
+ * a strip of L identical-width slices n = 1..L, slice Hamiltonians
+ * H_n = H0 + D_n (D_n: per-site on-site blocks, e.g. disorder), inter-slice
+ * hopping V = H_{n,n-1}, and two semi-infinite leads made by repeating the
+ * clean slice (H0, V) (section 5.3-B; the interface slices 1 and L belong to
+ * both system and lead).  The leads enter as self-energies Sigma_L on slice 1
+ * and Sigma_R on slice L; the retarded Green function is
+ * G = (E - H - Sigma_L - Sigma_R)^{-1} (Eq. (2), read with Im Sigma <= 0), and
+ * the transmission between the leads is T = Tr[Gamma_L G_1L Gamma_R G_1L^+]
+ * with Gamma = i (Sigma - Sigma^+) (section 2.3, T_kl and its Landauer
+ * conductance).  The basic recursive Green function algorithm (section 1)
+ * adds the slices one at a time from the left lead to the right lead; the
+ * local density of states comes from the reverse sweep (the "sewing" of
+ * section 5.3-D).
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) doubles: knit_z, the element
+ *     type of torch.complex128.  Matrices are row-major [M][M].
+ *   - Slice-local index of orbital o of site s is s * norb + o.
+ *   - Pointers documented as "device" point to GPU memory owned by the caller;
+ *     the library never allocates, frees or retains them.  Pointers documented
+ *     as "host" are read before the call returns.
+ *   - All device work is enqueued on `stream` (a hipStream_t; NULL = the
+ *     default stream) and is asynchronous with respect to the host.
+ *   - Arguments are validated on the host before any device call; a bad
+ *     argument returns KNIT_E_ARG and enqueues nothing.
+ *   - Numerical trouble in one problem never aborts a batch: it sets bits in
+ *     that problem's status word (KNIT_P_*), and its outputs are NaN.
+ *   - Work memory is supplied by the caller (`ws`, `ws_bytes`), sized by the
+ *     matching *_workspace() query; the calls perform no allocation.
+ *   - Calls on distinct streams with distinct workspaces are thread-safe.
+ */
+#ifndef KNIT_H
+#define KNIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNIT_ABI_VERSION 1
+#define KNIT_MAX_STRIPS 64     /* strip classes per batch */
+#define KNIT_MAX_M 1024        /* largest slice dimension */
+#define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
+
+typedef struct knit_z { double re, im; } knit_z;
+
+/* Return codes of every call. */
+enum {
+  KNIT_OK = 0,
+  KNIT_E_ARG = -1,          /* invalid argument (nothing was enqueued) */
+  KNIT_E_DEVICE = -2,       /* a HIP call failed */
+  KNIT_E_WORKSPACE = -3,    /* ws is NULL or ws_bytes is below the *_workspace() size */
+  KNIT_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+};
+
+/* Per-problem status bits (int32 per problem, written on the device). */
+enum {
+  KNIT_P_OK = 0,
+  KNIT_P_SINGULAR = 1,      /* an exactly singular slice (zero pivot) */
+  KNIT_P_NOCONV = 2,        /* decimation hit max_iter before convergence */
+  KNIT_P_NONFINITE = 4      /* NaN or Inf met in inputs or intermediates */
+};
+
+/* Arithmetic of the slice sweep. */
+enum {
+  KNIT_FP64 = 0,            /* FP64 throughout */
+  KNIT_FP32_REFINE = 1,     /* FP32 slice inverse and products, one FP64-residual
+                               refinement step on every slice inverse */
+  KNIT_FP32 = 2             /* FP32 slice inverse and products, no refinement */
+};
+
+/*
+ * A strip class: the clean slice shared by the system slices and both leads.
+ *   M     slice dimension W * norb (1 <= M <= KNIT_MAX_M)
+ *   norb  orbitals per site (1 <= norb <= KNIT_MAX_NORB, M % norb == 0)
+ *   H0    device [M][M]  clean intra-slice Hamiltonian (Hermitian)
+ *   vcol  device [W]     for each site a of slice n, the site of slice n-1 it
+ *                        is bonded to, or -1; no site of slice n-1 may appear
+ *                        twice (V is block-monomial)
+ *   vblk  device [W][norb][norb]  the hopping block H_{n,n-1}(a, vcol[a])
+ */
+typedef struct knit_strip {
+  int32_t M;
+  int32_t norb;
+  const knit_z *H0;
+  const int32_t *vcol;
+  const knit_z *vblk;
+} knit_strip;
+
+/*
+ * One problem of a batch: a strip instance (its on-site blocks) at one energy.
+ *   strip       index into the strip table of the call
+ *   L           number of slices (>= 1)
+ *   E           real energy
+ *   onsite_off  offset, in knit_z elements, of its on-site blocks
+ *               [L][W][norb][norb] in the `onsite` buffer
+ *   sigma_off   offset, in knit_z, of its Sigma_L / Sigma_R ([M][M]) in
+ *               `sigmaL` / `sigmaR` (problems at the same energy and strip
+ *               class may share one)
+ *   out_off     offset, in knit_z, of its G1N / GN1 / GNN blocks ([M][M])
+ *   ldos_off    offset, in doubles, of its LDOS [L][M]
+ * 48 bytes, no padding.
+ */
+typedef struct knit_problem {
+  int32_t strip;
+  int32_t L;
+  double E;
+  int64_t onsite_off;
+  int64_t sigma_off;
+  int64_t out_off;
+  int64_t ldos_off;
+} knit_problem;
+
+/* ABI version of the loaded library (KNIT_ABI_VERSION). */
+int knit_abi_version(void);
+
+/* Static text for a return code or a per-problem status bit set. */
+const char *knit_status_string(int code);
+
+/*
+ * Lead self-energies by decimation (section 2.3: the leads are integrated
+ * out into energy-dependent self-energies; section 7.1-B selfE).
+ *
+ * For each energy E[e] computes the surface Green function g of the
+ * semi-infinite lead at z = E + i*eta by renormalisation-group doubling
+ * (Lopez Sancho, Lopez Sancho and Rubio 1985), carried in double-double
+ * arithmetic (about 32 significant digits) so that the rounding growth of
+ * the doubling stays far below eta, then returns
+ *   side 0 (left lead):  Sigma_L = V g V^+,  g = (z - H0 - V g V^+)^{-1}
+ *   side 1 (right lead): Sigma_R = V^+ g V,  g = (z - H0 - V^+ g V)^{-1}
+ * Iteration stops when both decimated couplings fall below tol * scale
+ * (scale = max(1, max|H0|, max|V|)) or after max_iter steps (KNIT_P_NOCONV).
+ *
+ *   strip     host   strip class
+ *   side      0 = left lead, 1 = right lead
+ *   E         device [nE] energies
+ *   eta       broadening, > 0 (1e-13 recommended)
+ *   sigma     device [nE][M][M] output
+ *   iters     device [nE] output iteration counts, or NULL
+ *   pstatus   device [nE] output status words
+ */
+size_t knit_lead_selfenergy_workspace(const knit_strip *strip, int32_t nE);
+int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E, int32_t nE,
+                         double eta, double tol, int32_t max_iter, knit_z *sigma, int32_t *iters,
+                         int32_t *pstatus, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Left-to-right slice recursion (section 1, basic RGF) for a batch of P
+ * problems, in one persistent launch.  Per problem:
+ *   g_1 = (E - H_1 - Sigma_L - [L = 1] Sigma_R)^{-1}
+ *   g_n = (E - H_n - [n = L] Sigma_R - V g_{n-1} V^+)^{-1}
+ *   G_1n = G_{1,n-1} V^+ g_n,  G_n1 = g_n V G_{n-1,1},  G_11 = g_1
+ * and returns G_1L (G1N), optionally G_L1 (GN1) and G_LL = g_L (GNN).  Each
+ * slice inverse is a Gauss-Jordan elimination with partial pivoting (the
+ * pivot sequence of LU with partial pivoting, largest |re|+|im|, lowest
+ * row on ties).
+ *
+ *   strips, n_strips   host table of strip classes (n_strips <= KNIT_MAX_STRIPS)
+ *   probs_host         host [P] problem table (read before return)
+ *   probs_dev          device [P] copy of the same table
+ *   onsite             device on-site blocks addressed by onsite_off
+ *   sigmaL, sigmaR     device self-energies addressed by sigma_off
+ *   precision          KNIT_FP64, KNIT_FP32_REFINE or KNIT_FP32
+ *   G1N                device output addressed by out_off (required)
+ *   GN1, GNN           device outputs addressed by out_off, or NULL
+ *   pstatus            device [P] output status words
+ */
+size_t knit_rgf_sweep_workspace(const knit_strip *strips, int32_t n_strips,
+                                const knit_problem *probs_host, int32_t P, int32_t precision,
+                                int32_t want_gn1);
+int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                   const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+                   const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision, knit_z *G1N,
+                   knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/*
+ * Fisher-Lee transmission (section 2.3, T_kl), FP64, per problem:
+ *   T[p]      = Re Tr[Gamma_L G_1L Gamma_R G_1L^+]                 (required)
+ *   T_RL[p]   = Re Tr[Gamma_R G_L1 Gamma_L G_L1^+]                 (needs GN1)
+ *   T_ward[p] = Re{Tr[Gamma_R i(G_LL - G_LL^+)] - Tr[Gamma_R G_LL Gamma_R G_LL^+]}
+ *                                                                   (needs GNN)
+ * with Gamma = i (Sigma - Sigma^+).  T_RL and T_ward equal T when current is
+ * conserved; they are checks.  Output pointers other than T may be NULL.
+ */
+int knit_transmission(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                      const knit_problem *probs_dev, int32_t P, const knit_z *sigmaL,
+                      const knit_z *sigmaR, const knit_z *G1N, const knit_z *GN1,
+                      const knit_z *GNN, double *T, double *T_RL, double *T_ward, void *stream);
+
+/*
+ * Local density of states LDOS[p][n][i] = -Im (G_nn)_ii / pi on every slice
+ * (section 2.1 item b, the Green function at a given site; section 5.3-D
+ * sewing; section 7.1-D getG_retarded on-site).  A forward sweep keeps g_n
+ * every `checkpoint_stride` slices (the role of the paper's saving level),
+ * then the reverse sweep
+ *   G_LL = g_L,  G_nn = g_n + g_n V^+ G_{n+1,n+1} V g_n
+ * recomputes each segment's g_n from its checkpoint.  checkpoint_stride <= 0
+ * picks ceil(sqrt(L)).
+ *
+ *   ldos   device output addressed by ldos_off ([L][M] doubles per problem)
+ */
+size_t knit_ldos_workspace(const knit_strip *strips, int32_t n_strips,
+                           const knit_problem *probs_host, int32_t P, int32_t precision,
+                           int32_t checkpoint_stride);
+int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+              const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+              const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision,
+              int32_t checkpoint_stride, double *ldos, int32_t *pstatus, void *ws,
+              size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNIT_H */

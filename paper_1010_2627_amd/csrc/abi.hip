@@ -1,0 +1,189 @@
+// Host side of the C ABI declared in include/knit.h: argument validation
+// (before any HIP call), workspace sizing and kernel launches.
+
+#include <math.h>
+#include <string.h>
+
+#include "knit_internal.h"
+
+using namespace knit;
+
+namespace {
+
+bool strip_ok(const knit_strip *s) {
+  if (!s) return false;
+  if (s->M < 1 || s->M > KNIT_MAX_M) return false;
+  if (s->norb < 1 || s->norb > KNIT_MAX_NORB) return false;
+  if (s->M % s->norb != 0) return false;
+  if (!s->H0 || !s->vcol || !s->vblk) return false;
+  return true;
+}
+
+bool table_ok(const knit_strip *strips, int32_t n_strips) {
+  if (!strips || n_strips < 1 || n_strips > KNIT_MAX_STRIPS) return false;
+  for (int i = 0; i < n_strips; ++i)
+    if (!strip_ok(strips + i)) return false;
+  return true;
+}
+
+// Validates the problem table; returns largest M and L through the pointers.
+bool problems_ok(const knit_strip *strips, int32_t n_strips, const knit_problem *ph, int32_t P,
+                 int *Mmax, int *Lmax) {
+  if (P < 0) return false;
+  if (P > 0 && !ph) return false;
+  int mm = 0, lm = 0;
+  for (int i = 0; i < P; ++i) {
+    const knit_problem &p = ph[i];
+    if (p.strip < 0 || p.strip >= n_strips) return false;
+    if (p.L < 1) return false;
+    if (!isfinite(p.E)) return false;
+    if (p.onsite_off < 0 || p.sigma_off < 0 || p.out_off < 0 || p.ldos_off < 0) return false;
+    mm = strips[p.strip].M > mm ? strips[p.strip].M : mm;
+    lm = p.L > lm ? p.L : lm;
+  }
+  if (Mmax) *Mmax = mm;
+  if (Lmax) *Lmax = lm;
+  return true;
+}
+
+StripTable make_table(const knit_strip *strips, int32_t n) {
+  StripTable t;
+  memset(&t, 0, sizeof(t));
+  t.n = n;
+  for (int i = 0; i < n; ++i) t.s[i] = StripDev{strips[i].M, strips[i].norb, strips[i].H0, strips[i].vcol, strips[i].vblk};
+  return t;
+}
+
+bool precision_ok(int32_t p) { return p == KNIT_FP64 || p == KNIT_FP32_REFINE || p == KNIT_FP32; }
+
+int resolve_stride(int stride, int Lmax) {
+  if (stride > 0) return stride;
+  int s = (int)ceil(sqrt((double)Lmax));
+  return s < 1 ? 1 : s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int knit_abi_version(void) { return KNIT_ABI_VERSION; }
+
+const char *knit_status_string(int code) {
+  switch (code) {
+    case KNIT_OK: return "ok";
+    case KNIT_E_ARG: return "invalid argument";
+    case KNIT_E_DEVICE: return "HIP device error";
+    case KNIT_E_WORKSPACE: return "workspace missing or too small";
+    case KNIT_E_UNSUPPORTED: return "not supported by this build";
+    case KNIT_P_SINGULAR: return "singular slice";
+    case KNIT_P_NOCONV: return "decimation not converged";
+    case KNIT_P_NONFINITE: return "non-finite value";
+    default: return "combination of problem status bits or unknown code";
+  }
+}
+
+size_t knit_lead_selfenergy_workspace(const knit_strip *strip, int32_t nE) {
+  if (!strip_ok(strip) || nE < 0) return 0;
+  return (size_t)nE * decimation_bytes_per_energy(strip->M);
+}
+
+int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E, int32_t nE,
+                         double eta, double tol, int32_t max_iter, knit_z *sigma, int32_t *iters,
+                         int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
+  if (!strip_ok(strip)) return KNIT_E_ARG;
+  if (side != 0 && side != 1) return KNIT_E_ARG;
+  if (nE < 0) return KNIT_E_ARG;
+  if (!(eta > 0.0) || !isfinite(eta)) return KNIT_E_ARG;
+  if (!(tol > 0.0) || !isfinite(tol)) return KNIT_E_ARG;
+  if (max_iter < 1) return KNIT_E_ARG;
+  if (nE == 0) return KNIT_OK;
+  if (!E || !sigma || !pstatus) return KNIT_E_ARG;
+  const size_t need = knit_lead_selfenergy_workspace(strip, nE);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripDev s{strip->M, strip->norb, strip->H0, strip->vcol, strip->vblk};
+  hipError_t err = launch_decimation(s, side, E, nE, eta, tol, max_iter, sigma, iters, pstatus, ws,
+                                     decimation_bytes_per_energy(strip->M), (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+size_t knit_rgf_sweep_workspace(const knit_strip *strips, int32_t n_strips,
+                                const knit_problem *probs_host, int32_t P, int32_t precision,
+                                int32_t want_gn1) {
+  (void)want_gn1;
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips) || !precision_ok(precision)) return 0;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
+  if (P == 0) return 0;
+  return sweep_slab_bytes(Mmax, precision) * (size_t)sweep_grid(P);
+}
+
+int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                   const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+                   const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision, knit_z *G1N,
+                   knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes,
+                   void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips) || !precision_ok(precision)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !onsite || !sigmaL || !sigmaR || !G1N || !pstatus) return KNIT_E_ARG;
+  if (precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
+  const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, precision, GN1 != nullptr);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_sweep(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN,
+                                pstatus, ws, sweep_slab_bytes(Mmax, precision), Mmax,
+                                (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+int knit_transmission(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                      const knit_problem *probs_dev, int32_t P, const knit_z *sigmaL,
+                      const knit_z *sigmaR, const knit_z *G1N, const knit_z *GN1,
+                      const knit_z *GNN, double *T, double *T_RL, double *T_ward, void *stream) {
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, nullptr, nullptr)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !sigmaL || !sigmaR || !G1N || !T) return KNIT_E_ARG;
+  if (T_RL && !GN1) return KNIT_E_ARG;
+  if (T_ward && !GNN) return KNIT_E_ARG;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_transmission(tab, probs_dev, P, sigmaL, sigmaR, G1N, GN1, GNN, T, T_RL,
+                                       T_ward, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+size_t knit_ldos_workspace(const knit_strip *strips, int32_t n_strips,
+                           const knit_problem *probs_host, int32_t P, int32_t precision,
+                           int32_t checkpoint_stride) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips) || !precision_ok(precision)) return 0;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
+  if (P == 0) return 0;
+  const int st = resolve_stride(checkpoint_stride, Lmax);
+  const int grid = P < 1024 ? P : 1024;
+  return ldos_slab_bytes(Mmax, Lmax, st, precision) * (size_t)grid;
+}
+
+int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+              const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+              const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision,
+              int32_t checkpoint_stride, double *ldos, int32_t *pstatus, void *ws,
+              size_t ws_bytes, void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips) || !precision_ok(precision)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !onsite || !sigmaL || !sigmaR || !ldos || !pstatus) return KNIT_E_ARG;
+  if (precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
+  const int st = resolve_stride(checkpoint_stride, Lmax);
+  const size_t need = knit_ldos_workspace(strips, n_strips, probs_host, P, precision, checkpoint_stride);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_ldos(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, st, ldos, pstatus,
+                               ws, ldos_slab_bytes(Mmax, Lmax, st, precision), Mmax,
+                               (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+}  // extern "C"

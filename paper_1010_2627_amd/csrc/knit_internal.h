@@ -1,0 +1,63 @@
+// Internal declarations shared by the libknit host layer and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/knit.h"
+#include "knit_num.h"
+
+namespace knit {
+
+// Strip class as the kernels see it (device pointers, by value in kernel args).
+struct StripDev {
+  int M, norb;
+  const knit_z *H0;
+  const int32_t *vcol;
+  const knit_z *vblk;
+};
+
+struct StripTable {
+  int n;
+  StripDev s[KNIT_MAX_STRIPS];
+};
+
+// H0[a][b] and the dense inter-slice hopping V[a][b] = H_{n,n-1}(a, b) of a strip.
+__device__ __forceinline__ cpx<double> ld_z(const knit_z *p) { return {p->re, p->im}; }
+__device__ __forceinline__ void st_z(knit_z *p, cpx<double> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+__device__ __forceinline__ cpx<double> strip_V(const StripDev &s, int a, int b) {
+  const int no = s.norb;
+  const int sa = a / no, oa = a % no, sb = b / no, ob = b % no;
+  if (s.vcol[sa] != sb) return {0.0, 0.0};
+  return ld_z(s.vblk + ((int64_t)sa * no + oa) * no + ob);
+}
+
+// Launch wrappers (defined in the .hip files).
+hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta,
+                             double tol, int max_iter, knit_z *sigma, int32_t *iters,
+                             int32_t *pstatus, void *ws, size_t per_energy_bytes,
+                             hipStream_t stream);
+size_t decimation_bytes_per_energy(int M);
+
+size_t sweep_slab_bytes(int Mmax, int precision);
+int sweep_grid(int P);
+hipError_t launch_sweep(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                        const knit_z *sigmaL, const knit_z *sigmaR, int precision, knit_z *G1N,
+                        knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, size_t slab_bytes,
+                        int Mmax, hipStream_t stream);
+
+hipError_t launch_transmission(const StripTable &tab, const knit_problem *probs, int P,
+                               const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *G1N,
+                               const knit_z *GN1, const knit_z *GNN, double *T, double *T_RL,
+                               double *T_ward, hipStream_t stream);
+
+size_t ldos_slab_bytes(int Mmax, int Lmax, int stride, int precision);
+hipError_t launch_ldos(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                       const knit_z *sigmaL, const knit_z *sigmaR, int precision, int stride,
+                       double *ldos, int32_t *pstatus, void *ws, size_t slab_bytes, int Mmax,
+                       hipStream_t stream);
+
+}  // namespace knit

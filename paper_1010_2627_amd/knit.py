@@ -1,0 +1,269 @@
+"""Python binding of libknit (ctypes): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name declared
+in ``include/knit.h``; all arithmetic of the transport path runs in the HIP
+kernels of ``libknit.so``.  PyTorch provides device memory and the stream.
+If the library is not built this module raises at import time: there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libknit.so")
+
+KNIT_OK, KNIT_E_ARG, KNIT_E_DEVICE, KNIT_E_WORKSPACE, KNIT_E_UNSUPPORTED = 0, -1, -2, -3, -4
+KNIT_P_OK, KNIT_P_SINGULAR, KNIT_P_NOCONV, KNIT_P_NONFINITE = 0, 1, 2, 4
+KNIT_FP64, KNIT_FP32_REFINE, KNIT_FP32 = 0, 1, 2
+PRECISIONS = {"fp64": KNIT_FP64, "fp32_refine": KNIT_FP32_REFINE, "fp32": KNIT_FP32}
+KNIT_MAX_STRIPS = 64
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1010_2627_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class KnitStrip(ctypes.Structure):
+    _fields_ = [("M", c_i32), ("norb", c_i32), ("H0", c_vp), ("vcol", c_vp), ("vblk", c_vp)]
+
+
+PROBLEM_DTYPE = np.dtype([("strip", "<i4"), ("L", "<i4"), ("E", "<f8"), ("onsite_off", "<i8"),
+                          ("sigma_off", "<i8"), ("out_off", "<i8"), ("ldos_off", "<i8")], align=True)
+assert PROBLEM_DTYPE.itemsize == 48
+
+_SP = ctypes.POINTER(KnitStrip)
+
+_lib.knit_abi_version.restype = c_i32
+_lib.knit_status_string.restype = ctypes.c_char_p
+_lib.knit_status_string.argtypes = [c_i32]
+_lib.knit_lead_selfenergy_workspace.restype = c_sz
+_lib.knit_lead_selfenergy_workspace.argtypes = [_SP, c_i32]
+_lib.knit_lead_selfenergy.restype = c_i32
+_lib.knit_lead_selfenergy.argtypes = [_SP, c_i32, c_vp, c_i32, c_dbl, c_dbl, c_i32, c_vp, c_vp, c_vp,
+                                      c_vp, c_sz, c_vp]
+_lib.knit_rgf_sweep_workspace.restype = c_sz
+_lib.knit_rgf_sweep_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32, c_i32]
+_lib.knit_rgf_sweep.restype = c_i32
+_lib.knit_rgf_sweep.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp,
+                                c_vp, c_vp, c_vp, c_sz, c_vp]
+_lib.knit_transmission.restype = c_i32
+_lib.knit_transmission.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                   c_vp, c_vp, c_vp]
+_lib.knit_ldos_workspace.restype = c_sz
+_lib.knit_ldos_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32, c_i32]
+_lib.knit_ldos.restype = c_i32
+_lib.knit_ldos.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp,
+                           c_vp, c_sz, c_vp]
+
+EXPORTED = ["knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
+            "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
+            "knit_transmission", "knit_ldos_workspace", "knit_ldos"]
+
+
+class KnitError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+        self.code = code
+
+
+def abi_version() -> int:
+    return int(_lib.knit_abi_version())
+
+
+def status_string(code: int) -> str:
+    return _lib.knit_status_string(int(code)).decode()
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return t.data_ptr() if t.numel() > 0 else None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return int(t)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check(code: int, where: str):
+    if code != KNIT_OK:
+        raise KnitError(code, where)
+
+
+def _z(t: torch.Tensor) -> torch.Tensor:
+    assert t.dtype == torch.complex128 and t.is_contiguous()
+    return t
+
+
+# ---------------------------------------------------------------- device-side inputs
+
+@dataclass
+class DeviceStrip:
+    """A strip class resident on the GPU (tensors keep the memory alive)."""
+
+    M: int
+    norb: int
+    H0: torch.Tensor      # [M, M] complex128
+    vcol: torch.Tensor    # [W] int32
+    vblk: torch.Tensor    # [W, norb, norb] complex128
+
+    @classmethod
+    def from_host(cls, strip, device="cuda"):
+        return cls(strip.M, strip.norb,
+                   torch.from_numpy(np.ascontiguousarray(strip.H0)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(strip.vcol, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(strip.vblk)).to(device))
+
+    def c(self) -> KnitStrip:
+        return KnitStrip(self.M, self.norb, _ptr(self.H0), _ptr(self.vcol), _ptr(self.vblk))
+
+
+def strip_table(strips) -> ctypes.Array:
+    arr = (KnitStrip * len(strips))()
+    for i, s in enumerate(strips):
+        arr[i] = s.c() if isinstance(s, DeviceStrip) else s
+    return arr
+
+
+@dataclass
+class ProblemTable:
+    host: np.ndarray          # PROBLEM_DTYPE [P]
+    dev: torch.Tensor         # uint8 [P * 48] on the device
+
+    @classmethod
+    def from_host(cls, host: np.ndarray, device="cuda"):
+        host = np.ascontiguousarray(host, dtype=PROBLEM_DTYPE)
+        dev = torch.from_numpy(host.view(np.uint8).copy()).to(device)
+        return cls(host, dev)
+
+    @property
+    def P(self) -> int:
+        return int(self.host.shape[0])
+
+
+# ---------------------------------------------------------------- entry points
+
+def knit_lead_selfenergy(strip: DeviceStrip, side: int, E: torch.Tensor, eta: float = 1e-13,
+                         tol: float = 1e-16, max_iter: int = 100, stream=None):
+    """Sigma of the left (side 0) or right (side 1) lead at energies E (device float64 [nE]).
+
+    Returns (sigma [nE, M, M] complex128, iters [nE] int32, status [nE] int32), all on the device.
+    """
+    assert E.dtype == torch.float64 and E.is_cuda and E.is_contiguous()
+    nE = E.numel()
+    dev = E.device
+    sigma = torch.empty((nE, strip.M, strip.M), dtype=torch.complex128, device=dev)
+    iters = torch.zeros(nE, dtype=torch.int32, device=dev)
+    status = torch.zeros(nE, dtype=torch.int32, device=dev)
+    cs = strip.c()
+    wsz = _lib.knit_lead_selfenergy_workspace(ctypes.byref(cs), nE)
+    ws = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_lead_selfenergy(ctypes.byref(cs), int(side), _ptr(E), nE, float(eta), float(tol),
+                                     int(max_iter), _ptr(sigma), _ptr(iters), _ptr(status), _ptr(ws),
+                                     wsz, _stream(stream))
+    _check(code, "knit_lead_selfenergy")
+    return sigma, iters, status
+
+
+def knit_rgf_sweep(strips, probs: ProblemTable, onsite: torch.Tensor, sigmaL: torch.Tensor,
+                   sigmaR: torch.Tensor, precision="fp64", G1N: torch.Tensor = None,
+                   GN1: torch.Tensor | bool = False, GNN: torch.Tensor | bool = False, stream=None,
+                   workspace: torch.Tensor | None = None):
+    """Slice sweep for every problem of ``probs``; returns (G1N, GN1|None, GNN|None, status).
+
+    Output buffers are allocated (flat complex128, sized from out_off + M^2) unless given.
+    """
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    need = _out_elems(strips, probs)
+    if G1N is None:
+        G1N = torch.empty(need, dtype=torch.complex128, device=dev)
+    if GN1 is True:
+        GN1 = torch.empty(need, dtype=torch.complex128, device=dev)
+    if GNN is True:
+        GNN = torch.empty(need, dtype=torch.complex128, device=dev)
+    GN1 = GN1 if isinstance(GN1, torch.Tensor) else None
+    GNN = GNN if isinstance(GNN, torch.Tensor) else None
+    status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    wsz = _lib.knit_rgf_sweep_workspace(tab, len(strips), _ptr(probs.host), P, prec, GN1 is not None)
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_rgf_sweep(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
+                               _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), prec, _ptr(G1N), _ptr(GN1),
+                               _ptr(GNN), _ptr(status), _ptr(workspace), workspace.numel(),
+                               _stream(stream))
+    _check(code, "knit_rgf_sweep")
+    return G1N, GN1, GNN, status[:P]
+
+
+def knit_rgf_sweep_workspace(strips, probs: ProblemTable, precision="fp64", want_gn1=False) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tab = strip_table(strips)
+    return int(_lib.knit_rgf_sweep_workspace(tab, len(strips), _ptr(probs.host), probs.P, prec,
+                                             int(want_gn1)))
+
+
+def knit_transmission(strips, probs: ProblemTable, sigmaL, sigmaR, G1N, GN1=None, GNN=None,
+                      stream=None):
+    """Returns (T, T_RL|None, T_ward|None) as device float64 [P]."""
+    tab = strip_table(strips)
+    dev = G1N.device
+    P = probs.P
+    T = torch.empty(P, dtype=torch.float64, device=dev)
+    T_RL = torch.empty(P, dtype=torch.float64, device=dev) if GN1 is not None else None
+    T_w = torch.empty(P, dtype=torch.float64, device=dev) if GNN is not None else None
+    code = _lib.knit_transmission(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P,
+                                  _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(G1N), _ptr(GN1), _ptr(GNN),
+                                  _ptr(T), _ptr(T_RL), _ptr(T_w), _stream(stream))
+    _check(code, "knit_transmission")
+    return T, T_RL, T_w
+
+
+def knit_ldos(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, precision="fp64",
+              checkpoint_stride: int = 0, stream=None):
+    """Returns (ldos flat float64 addressed by ldos_off, status [P])."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    n = 0
+    for p in probs.host:
+        M = _strip_M(strips[int(p["strip"])])
+        n = max(n, int(p["ldos_off"]) + int(p["L"]) * M)
+    ldos = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    wsz = _lib.knit_ldos_workspace(tab, len(strips), _ptr(probs.host), P, prec, int(checkpoint_stride))
+    ws = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_ldos(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
+                          _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), prec, int(checkpoint_stride), _ptr(ldos),
+                          _ptr(status), _ptr(ws), int(wsz), _stream(stream))
+    _check(code, "knit_ldos")
+    return ldos, status[:P]
+
+
+def _strip_M(s) -> int:
+    return int(s.M)
+
+
+def _out_elems(strips, probs: ProblemTable) -> int:
+    n = 1
+    for p in probs.host:
+        M = _strip_M(strips[int(p["strip"])])
+        n = max(n, int(p["out_off"]) + M * M)
+    return n

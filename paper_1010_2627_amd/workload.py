@@ -1,0 +1,187 @@
+"""Batches of transport problems on the GPU: packing and driving the C ABI.
+
+A batch is a set of strip realizations (a strip class plus its seeded on-site
+blocks) crossed with the energies of their strip class.  This module packs
+the host data into the flat device buffers and the problem table that
+``libknit`` expects, and calls the entry points in order (lead self-energies,
+sweep, transmission, LDOS).  It holds no transport arithmetic.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import inputs
+from . import knit as K
+
+
+@dataclass
+class Realization:
+    strip: int               # index into Batch.strips
+    onsite: np.ndarray       # [L, W, norb, norb] complex128
+    label: str = ""
+
+
+@dataclass
+class Batch:
+    strips: list                      # inputs.Strip (host)
+    realizations: list                # Realization
+    energies: list                    # per strip class: float64 array of energies
+    device: str = "cuda"
+    dstrips: list = field(default_factory=list)
+    probs: K.ProblemTable | None = None
+    onsite: torch.Tensor | None = None
+    sigmaL: torch.Tensor | None = None
+    sigmaR: torch.Tensor | None = None
+    sigma_status: torch.Tensor | None = None
+    sigma_iters: torch.Tensor | None = None
+    prob_meta: np.ndarray | None = None      # [P, 2]: (realization, energy index)
+
+    def __post_init__(self):
+        assert len(self.energies) == len(self.strips)
+        self.dstrips = [K.DeviceStrip.from_host(s, self.device) for s in self.strips]
+        # on-site blocks, concatenated
+        offs, chunks, pos = [], [], 0
+        for r in self.realizations:
+            st = self.strips[r.strip]
+            assert r.onsite.shape[1:] == (st.W, st.norb, st.norb)
+            offs.append(pos)
+            chunks.append(np.ascontiguousarray(r.onsite, dtype=np.complex128).reshape(-1))
+            pos += chunks[-1].size
+        flat = np.concatenate(chunks) if chunks else np.zeros(1, np.complex128)
+        self.onsite = torch.from_numpy(flat).to(self.device)
+        # sigma slots: one per (strip class, energy)
+        self.sigma_base = []
+        spos = 0
+        for s, E in zip(self.strips, self.energies):
+            self.sigma_base.append(spos)
+            spos += len(E) * s.M * s.M
+        self.sigma_elems = max(spos, 1)
+        # problems: realization x energy of its strip class
+        rows, meta = [], []
+        out_pos = ldos_pos = 0
+        for ri, r in enumerate(self.realizations):
+            st = self.strips[r.strip]
+            L = r.onsite.shape[0]
+            for ei, E in enumerate(self.energies[r.strip]):
+                rows.append((r.strip, L, float(E), offs[ri],
+                             self.sigma_base[r.strip] + ei * st.M * st.M, out_pos, ldos_pos))
+                meta.append((ri, ei))
+                out_pos += st.M * st.M
+                ldos_pos += L * st.M
+        host = np.array(rows, dtype=K.PROBLEM_DTYPE) if rows else np.zeros(0, K.PROBLEM_DTYPE)
+        self.probs = K.ProblemTable.from_host(host, self.device)
+        self.prob_meta = np.array(meta, dtype=np.int64).reshape(-1, 2)
+
+    @property
+    def P(self) -> int:
+        return self.probs.P
+
+    def slice_steps(self) -> int:
+        return int(self.probs.host["L"].sum())
+
+    def compute_sigmas(self, eta=1e-13, tol=1e-16, max_iter=100, stream=None):
+        self.sigmaL = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        self.sigmaR = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        stats, its = [], []
+        for si, (ds, E) in enumerate(zip(self.dstrips, self.energies)):
+            if len(E) == 0:
+                continue
+            Et = torch.as_tensor(np.asarray(E, dtype=np.float64), device=self.device)
+            base, n = self.sigma_base[si], len(E) * ds.M * ds.M
+            for side, dst in ((0, self.sigmaL), (1, self.sigmaR)):
+                sig, it, st = K.knit_lead_selfenergy(ds, side, Et, eta, tol, max_iter, stream)
+                dst[base:base + n].copy_(sig.reshape(-1))
+                stats.append(st)
+                its.append(it)
+        self.sigma_status = torch.cat(stats) if stats else None
+        self.sigma_iters = torch.cat(its) if its else None
+        return self.sigmaL, self.sigmaR
+
+    def set_sigmas(self, sigL_list, sigR_list):
+        """Install externally computed self-energies: one [nE, M, M] array per strip class."""
+        self.sigmaL = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        self.sigmaR = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        for si, (sl, sr) in enumerate(zip(sigL_list, sigR_list)):
+            base = self.sigma_base[si]
+            n = np.asarray(sl).size
+            self.sigmaL[base:base + n] = torch.from_numpy(np.ascontiguousarray(sl).reshape(-1)).to(self.device)
+            self.sigmaR[base:base + n] = torch.from_numpy(np.ascontiguousarray(sr).reshape(-1)).to(self.device)
+
+    def sigma_of(self, p: int):
+        """(Sigma_L, Sigma_R) of problem p as [M, M] device views."""
+        row = self.probs.host[p]
+        M = self.strips[int(row["strip"])].M
+        o = int(row["sigma_off"])
+        return self.sigmaL[o:o + M * M].view(M, M), self.sigmaR[o:o + M * M].view(M, M)
+
+    def sweep(self, precision="fp64", gn1=False, gnn=True, stream=None, workspace=None):
+        return K.knit_rgf_sweep(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR,
+                                precision, GN1=gn1, GNN=gnn, stream=stream, workspace=workspace)
+
+    def transmission(self, G1N, GN1=None, GNN=None, stream=None):
+        return K.knit_transmission(self.dstrips, self.probs, self.sigmaL, self.sigmaR, G1N, GN1, GNN,
+                                   stream)
+
+    def ldos(self, precision="fp64", checkpoint_stride=0, stream=None):
+        return K.knit_ldos(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR, precision,
+                           checkpoint_stride, stream)
+
+    def block(self, flat: torch.Tensor, p: int) -> torch.Tensor:
+        row = self.probs.host[p]
+        M = self.strips[int(row["strip"])].M
+        o = int(row["out_off"])
+        return flat[o:o + M * M].view(M, M)
+
+    def ldos_block(self, flat: torch.Tensor, p: int) -> torch.Tensor:
+        row = self.probs.host[p]
+        M = self.strips[int(row["strip"])].M
+        o = int(row["ldos_off"])
+        return flat[o:o + int(row["L"]) * M].view(int(row["L"]), M)
+
+
+# ---------------------------------------------------------------- the synthetic workloads
+
+def square_batch(W, L, w, n_energies, n_seeds, emin=-3.9, emax=3.9, device="cuda", seed0=None):
+    """Square-lattice strip, Anderson disorder U[-w/2, w/2], midpoint energies, n_seeds realizations."""
+    st = inputs.square_strip(W)
+    seed0 = inputs.SEED_BASE if seed0 is None else seed0
+    reals = [Realization(0, inputs.onsite_disorder(st, L, w, seed0 + r), f"seed{seed0 + r}")
+             for r in range(n_seeds)]
+    return Batch([st], reals, [inputs.midpoint_grid(emin, emax, n_energies)], device)
+
+
+def rashba_batch(W, L, w, n_energies, n_seeds, alpha=0.2, ez=0.1, emin=-3.9, emax=3.9,
+                 device="cuda", seed0=None):
+    st = inputs.rashba_strip(W, alpha=alpha, ez=ez)
+    seed0 = inputs.SEED_BASE if seed0 is None else seed0
+    reals = [Realization(0, inputs.onsite_disorder(st, L, w, seed0 + r), f"seed{seed0 + r}")
+             for r in range(n_seeds)]
+    return Batch([st], reals, [inputs.midpoint_grid(emin, emax, n_energies)], device)
+
+
+def zigzag_batch(Nz, L, w, energies, n_seeds, device="cuda", seed0=None):
+    st = inputs.zigzag_strip(Nz)
+    seed0 = inputs.SEED_BASE if seed0 is None else seed0
+    reals = [Realization(0, inputs.onsite_disorder(st, L, w, seed0 + r), f"seed{seed0 + r}")
+             for r in range(n_seeds)]
+    return Batch([st], reals, [np.asarray(energies, dtype=np.float64)], device)
+
+
+def uneven_batch(n_strips=512, n_energies=32, emin=-3.9, emax=3.9, device="cuda", **layout_kw):
+    """Strips of uneven width and length (one strip class per width), 32 energies each."""
+    lay = inputs.uneven_layout(n_strips, **layout_kw)
+    widths = sorted(set(int(x) for x in lay.widths))
+    classes = {W: i for i, W in enumerate(widths)}
+    strips = [inputs.square_strip(W) for W in widths]
+    reals = []
+    for i in range(n_strips):
+        st = strips[classes[int(lay.widths[i])]]
+        reals.append(Realization(classes[int(lay.widths[i])],
+                                 inputs.onsite_disorder(st, int(lay.lengths[i]), float(lay.ws[i]),
+                                                        int(lay.seeds[i])), f"strip{i}"))
+    E = inputs.midpoint_grid(emin, emax, n_energies)
+    return Batch(strips, reals, [E for _ in strips], device)

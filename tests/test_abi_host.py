@@ -1,0 +1,154 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/knit.h declares, and
+reject bad arguments on the host, before any HIP call, with KNIT_E_ARG or
+KNIT_E_WORKSPACE.  Device pointers passed here are fake, non-null addresses:
+every call below fails validation, so none is ever dereferenced.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1010_2627_amd", "libknit.so")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not os.path.exists(LIB):
+        from paper_1010_2627_amd import build
+        build.build()
+    from paper_1010_2627_amd import knit
+    return knit
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "knit.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(knit_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(K):
+    names = _declared()
+    assert len(names) >= 9
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(K.EXPORTED) == names
+
+
+def test_abi_version_and_status_strings(K):
+    assert K.abi_version() == 1
+    assert K.status_string(K.KNIT_E_ARG) == "invalid argument"
+    assert "singular" in K.status_string(K.KNIT_P_SINGULAR)
+
+
+FAKE = 0x1000   # never dereferenced: validation fails first
+
+
+def _strip(M=4, norb=1, H0=FAKE, vcol=FAKE, vblk=FAKE):
+    from paper_1010_2627_amd.knit import KnitStrip
+    return KnitStrip(M, norb, H0, vcol, vblk)
+
+
+def _probs(rows):
+    from paper_1010_2627_amd.knit import PROBLEM_DTYPE
+    return np.array(rows, dtype=PROBLEM_DTYPE)
+
+
+def _sweep(K, strips, probs, **kw):
+    arr = (K.KnitStrip * len(strips))(*strips) if strips else None
+    a = dict(n=len(strips), pd=FAKE, onsite=FAKE, sL=FAKE, sR=FAKE, prec=0, G1N=FAKE, GN1=None,
+             GNN=None, st=FAKE, ws=FAKE, wsb=1 << 40, stream=None)
+    a.update(kw)
+    ph = probs.ctypes.data if probs is not None and len(probs) else (None if probs is None else probs.ctypes.data)
+    return K._lib.knit_rgf_sweep(arr, a["n"], ph, a["pd"], len(probs) if probs is not None else 0,
+                                 a["onsite"], a["sL"], a["sR"], a["prec"], a["G1N"], a["GN1"], a["GNN"],
+                                 a["st"], a["ws"], a["wsb"], a["stream"])
+
+
+def test_sweep_rejects_bad_strip_descriptions(K):
+    good = _probs([(0, 8, 0.1, 0, 0, 0, 0)])
+    assert _sweep(K, [_strip(M=0)], good) == K.KNIT_E_ARG
+    assert _sweep(K, [_strip(M=5, norb=2)], good) == K.KNIT_E_ARG          # norb does not divide M
+    assert _sweep(K, [_strip(norb=0)], good) == K.KNIT_E_ARG
+    assert _sweep(K, [_strip(M=4096)], good) == K.KNIT_E_ARG               # above KNIT_MAX_M
+    assert _sweep(K, [_strip(H0=None)], good) == K.KNIT_E_ARG
+    assert _sweep(K, [_strip(vcol=None)], good) == K.KNIT_E_ARG
+    assert _sweep(K, [], good, n=0) == K.KNIT_E_ARG
+
+
+def test_sweep_rejects_bad_problems(K):
+    s = [_strip()]
+    assert _sweep(K, s, _probs([(1, 8, 0.1, 0, 0, 0, 0)])) == K.KNIT_E_ARG    # strip index
+    assert _sweep(K, s, _probs([(0, 0, 0.1, 0, 0, 0, 0)])) == K.KNIT_E_ARG    # L < 1
+    assert _sweep(K, s, _probs([(0, 4, np.nan, 0, 0, 0, 0)])) == K.KNIT_E_ARG  # E not finite
+    assert _sweep(K, s, _probs([(0, 4, 0.1, -1, 0, 0, 0)])) == K.KNIT_E_ARG   # negative offset
+    good = _probs([(0, 4, 0.1, 0, 0, 0, 0)])
+    assert _sweep(K, s, good, prec=7) == K.KNIT_E_ARG                           # precision
+    assert _sweep(K, s, good, G1N=None) == K.KNIT_E_ARG                         # missing output
+    assert _sweep(K, s, good, st=None) == K.KNIT_E_ARG
+    assert _sweep(K, s, good, pd=None) == K.KNIT_E_ARG
+
+
+def test_sweep_workspace_checks(K):
+    s = [_strip(M=16)]
+    probs = _probs([(0, 8, 0.1, 0, 0, 0, 0), (0, 8, 0.2, 0, 0, 256, 0)])
+    arr = (K.KnitStrip * 1)(*s)
+    need = K._lib.knit_rgf_sweep_workspace(arr, 1, probs.ctypes.data, 2, 0, 0)
+    assert need > 0
+    need32 = K._lib.knit_rgf_sweep_workspace(arr, 1, probs.ctypes.data, 2, 2, 0)
+    assert 0 < need32 < need
+    assert _sweep(K, s, probs, wsb=need - 1) == K.KNIT_E_WORKSPACE
+    assert _sweep(K, s, probs, ws=None) == K.KNIT_E_WORKSPACE
+    # invalid requests size to 0
+    assert K._lib.knit_rgf_sweep_workspace(arr, 1, probs.ctypes.data, 2, 9, 0) == 0
+
+
+def test_empty_batch_is_ok_without_device(K):
+    s = [_strip()]
+    assert _sweep(K, s, _probs([])) == K.KNIT_OK
+
+
+def test_selfenergy_argument_checks(K):
+    s = _strip(M=8)
+    E = FAKE
+    f = K._lib.knit_lead_selfenergy
+    ws_need = K._lib.knit_lead_selfenergy_workspace(ctypes.byref(s), 3)
+    assert ws_need > 0
+    args = lambda **kw: dict(dict(side=0, E=E, nE=3, eta=1e-13, tol=1e-16, it=50, sig=FAKE, iters=None,
+                                  st=FAKE, ws=FAKE, wsb=ws_need), **kw)
+    def call(**kw):
+        a = args(**kw)
+        return f(ctypes.byref(s), a["side"], a["E"], a["nE"], a["eta"], a["tol"], a["it"], a["sig"],
+                 a["iters"], a["st"], a["ws"], a["wsb"], None)
+    assert call(side=2) == K.KNIT_E_ARG
+    assert call(eta=0.0) == K.KNIT_E_ARG
+    assert call(eta=float("inf")) == K.KNIT_E_ARG
+    assert call(tol=-1.0) == K.KNIT_E_ARG
+    assert call(it=0) == K.KNIT_E_ARG
+    assert call(nE=-1) == K.KNIT_E_ARG
+    assert call(sig=None) == K.KNIT_E_ARG
+    assert call(E=None) == K.KNIT_E_ARG
+    assert call(wsb=ws_need - 1) == K.KNIT_E_WORKSPACE
+    assert call(nE=0) == K.KNIT_OK
+    bad = _strip(M=6, norb=4)
+    assert f(ctypes.byref(bad), 0, E, 3, 1e-13, 1e-16, 50, FAKE, None, FAKE, FAKE, 1 << 40, None) == K.KNIT_E_ARG
+
+
+def test_transmission_and_ldos_argument_checks(K):
+    s = (K.KnitStrip * 1)(_strip())
+    probs = _probs([(0, 4, 0.1, 0, 0, 0, 0)])
+    t = K._lib.knit_transmission
+    assert t(s, 1, probs.ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, None, None, None, None, None, None) == K.KNIT_E_ARG
+    # T_RL requested without GN1
+    assert t(s, 1, probs.ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, None, None, FAKE, FAKE, None, None) == K.KNIT_E_ARG
+    ld = K._lib.knit_ldos
+    need = K._lib.knit_ldos_workspace(s, 1, probs.ctypes.data, 1, 0, 0)
+    assert need > 0
+    assert ld(s, 1, probs.ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, 0, 0, FAKE, FAKE, FAKE, need - 1, None) == K.KNIT_E_WORKSPACE
+    assert ld(s, 1, probs.ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, 0, 0, None, FAKE, FAKE, need, None) == K.KNIT_E_ARG
