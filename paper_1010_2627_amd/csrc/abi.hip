@@ -114,6 +114,8 @@ size_t knit_rgf_sweep_workspace(const knit_strip *strips, int32_t n_strips,
   if (!table_ok(strips, n_strips) || !precision_ok(precision)) return 0;
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
   if (P == 0) return 0;
+  if (sweep_mfma_supports(Mmax)) return sweep_mfma_workspace(Mmax, precision, P);
+  if (precision == KNIT_FP32_REFINE) return 0;
   return sweep_slab_bytes(Mmax, precision) * (size_t)sweep_grid(P);
 }
 
@@ -127,13 +129,18 @@ int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_proble
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
   if (P == 0) return KNIT_OK;
   if (!probs_dev || !onsite || !sigmaL || !sigmaR || !G1N || !pstatus) return KNIT_E_ARG;
-  if (precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
+  const bool fast = sweep_mfma_supports(Mmax);
+  if (!fast && precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
   const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, precision, GN1 != nullptr);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
   StripTable tab = make_table(strips, n_strips);
-  hipError_t err = launch_sweep(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN,
-                                pstatus, ws, sweep_slab_bytes(Mmax, precision), Mmax,
-                                (hipStream_t)stream);
+  hipError_t err;
+  if (fast)
+    err = launch_sweep_mfma(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN, pstatus, ws,
+                            Mmax, (hipStream_t)stream);
+  else
+    err = launch_sweep(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN, pstatus, ws,
+                       sweep_slab_bytes(Mmax, precision), Mmax, (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 

@@ -42,6 +42,15 @@ hipError_t launch_decimation(const StripDev &s, int side, const double *E, int n
                              hipStream_t stream);
 size_t decimation_bytes_per_energy(int M);
 
+constexpr int SWEEP_MAX_GRID = 512;   // upper bound of resident sweep workgroups
+
+bool sweep_mfma_supports(int Mmax);
+size_t sweep_mfma_workspace(int Mmax, int precision, int P);
+hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                             const knit_z *sigmaL, const knit_z *sigmaR, int precision, knit_z *G1N,
+                             knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, int Mmax,
+                             hipStream_t stream);
+
 size_t sweep_slab_bytes(int Mmax, int precision);
 int sweep_grid(int P);
 hipError_t launch_sweep(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
