@@ -34,44 +34,68 @@ namespace knit {
 
 namespace {
 
-constexpr int NT2 = 512;   // threads per workgroup: one panel row per thread
 constexpr int MPAD = 32;   // slice dimension padding
-// panel width = wave tile edge: 16 for FP64 (a 32-wide FP64 panel row would not
-// fit the register file next to the MFMA tiles), 32 for FP32
+// inner panel width = wave tile edge of the inner phases
 template <class RG> struct PanelW;
 template <> struct PanelW<double> { static constexpr int NB = 16; };
 template <> struct PanelW<float> { static constexpr int NB = 16; };
 
-__device__ __forceinline__ void wg_argmax8(double &v, int &i, double *sv, int *si) {
-  for (int off = 32; off > 0; off >>= 1) {
-    double v2 = __shfl_xor(v, off, 64);
-    int i2 = __shfl_xor(i, off, 64);
-    argmax_merge(v, i, v2, i2);
-  }
+extern "C" __device__ unsigned int __ockl_wfred_max_u32(unsigned int);
+
+// Workgroup argmax of a non-negative magnitude, lowest index on ties.  Each
+// thread offers (v, idx) or v < 0 for "no candidate".  The key is the float
+// bit pattern of v (monotonic for v >= 0) and the complement of idx, reduced
+// by two 32-bit wavefront max-reductions and one LDS exchange across waves.
+// key (double buffered by the caller: one barrier suffices) holds 2 words per wave.
+__device__ __forceinline__ void wg_argmax_key(double v, int idx, unsigned int *key, float &vbest,
+                                              int &ibest) {
+  const bool valid = v >= 0.0 || v != v;
+  const unsigned int hi = valid ? __float_as_uint((float)v) : 0u;
+  const unsigned int whi = __ockl_wfred_max_u32(hi);
+  const unsigned int lo = (valid && hi == whi) ? 0xffffffffu - (unsigned int)idx : 0u;
+  const unsigned int wlo = __ockl_wfred_max_u32(lo);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) {
-    sv[w] = v;
-    si[w] = i;
+    key[2 * w] = whi;
+    key[2 * w + 1] = wlo;
   }
   __syncthreads();
-  v = sv[0];
-  i = si[0];
+  unsigned int bh = key[0], bl = key[1];
   const int nw = blockDim.x >> 6;
-  for (int k = 1; k < nw; ++k) argmax_merge(v, i, sv[k], si[k]);
-  __syncthreads();
+  for (int k = 1; k < nw; ++k) {
+    const unsigned int h = key[2 * k], l2 = key[2 * k + 1];
+    if (h > bh || (h == bh && l2 > bl)) {
+      bh = h;
+      bl = l2;
+    }
+  }
+  vbest = bl ? __uint_as_float(bh) : -1.0f;
+  ibest = bl ? (int)(0xffffffffu - bl) : 0x7fffffff;
 }
 
-// Phase 1.  Requires Mp <= blockDim.x.  Returns status bits.  The pivot loop
-// is not unrolled: register column j is picked with selects, which keeps the
-// panel row (NB complex values) in registers without spilling.
+// Rows of X are addressed through a logical -> physical map: pivoting permutes
+// the map (kept in LDS), never the rows in memory.  Rows >= Mp (the stacked
+// propagator rows) are never permuted.
+struct RowMap {
+  const int *phys;
+  int Mp;
+  __device__ __forceinline__ int operator()(int r) const { return r < Mp ? phys[r] : r; }
+};
+
+// Phase 1: elimination restricted to the NB panel columns [k0, k0+NB) and the
+// candidate rows [k0, Mp), one logical row per thread (requires Mp <=
+// blockDim.x).  Pivot: largest |re|+|im| in the column among rows not yet
+// used, lowest row on ties.  The pivot loop is not unrolled: register column
+// j is picked with selects.  Returns status bits.
 template <class RG, int NB = PanelW<RG>::NB>
-__device__ int gj_panel(cpx<RG> *X, int Mp, int k0, int *q, cpx<RG> *xchg, cpx<RG> *prow, double *sv,
+__device__ int gj_panel(cpx<RG> *X, int Mp, int k0, int *phys, cpx<RG> *xchg, cpx<RG> *prow, double *sv,
                         int *si) {
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x;
   const bool cand = t >= k0 && t < Mp;
+  const int64_t myrow = cand ? (int64_t)phys[t] * Mp : 0;
   cpx<RG> x[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = cand ? X[(int64_t)t * Mp + k0 + c] : c_zero<RG>();
+  for (int c = 0; c < NB; ++c) x[c] = cand ? X[myrow + k0 + c] : c_zero<RG>();
   int flags = 0;
 #pragma unroll 1
   for (int j = 0; j < NB; ++j) {
@@ -80,199 +104,328 @@ __device__ int gj_panel(cpx<RG> *X, int Mp, int k0, int *q, cpx<RG> *xchg, cpx<R
 #pragma unroll
     for (int c = 1; c < NB; ++c)
       if (c == j) xj = x[c];
-    double v = -1.0;
-    int idx = 0x7fffffff;
-    if (t >= pj && t < Mp) {
-      v = c_abs1(xj);
-      idx = t;
-    }
-    wg_argmax8(v, idx, sv, si);
+    float vb;
+    int idx;
+    wg_argmax_key((t >= pj && t < Mp) ? c_abs1(xj) : -1.0, t, reinterpret_cast<unsigned int *>(si) + (j & 1) * 32,
+                  vb, idx);
     const int p = (idx >= pj && idx < Mp) ? idx : pj;
-    if (!(v > 0.0)) flags |= (v == 0.0) ? KNIT_P_SINGULAR : KNIT_P_NONFINITE;
-    if (!isfinite(v)) flags |= KNIT_P_NONFINITE;
-    if (p != pj) {
-      if (t == p)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) xchg[c] = x[c];
-      if (t == pj)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) xchg[NB + c] = x[c];
-      for (int c = t; c < Mp; c += nt) {
-        if (c >= k0 && c < k0 + NB) continue;
-        cpx<RG> a = X[(int64_t)pj * Mp + c], b = X[(int64_t)p * Mp + c];
-        X[(int64_t)pj * Mp + c] = b;
-        X[(int64_t)p * Mp + c] = a;
-      }
-      if (t == 0) {
-        int s2 = q[pj];
-        q[pj] = q[p];
-        q[p] = s2;
-      }
-      __syncthreads();
-      if (t == pj)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) x[c] = xchg[c];
-      if (t == p)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) x[c] = xchg[NB + c];
-      xj = x[0];
-#pragma unroll
-      for (int c = 1; c < NB; ++c)
-        if (c == j) xj = x[c];
-    }
-    if (t == pj) {
+    if (!(vb > 0.0f)) flags |= (vb == 0.0f) ? KNIT_P_SINGULAR : KNIT_P_NONFINITE;
+    if (!isfinite(vb)) flags |= KNIT_P_NONFINITE;
+    // the pivot row (at position p) moves to position pj, scaled; the row at pj moves to p
+    if (t == p) {
       const cpx<RG> d = c_inv(xj);
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        x[c] = (c == j) ? d : c_mul(x[c], d);
-        prow[c] = x[c];
-      }
+      for (int c = 0; c < NB; ++c) prow[c] = (c == j) ? d : c_mul(x[c], d);
+    }
+    if (t == pj && p != pj)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) xchg[c] = x[c];
+    if (t == 0 && p != pj) {
+      const int s2 = phys[pj];
+      phys[pj] = phys[p];
+      phys[p] = s2;
     }
     __syncthreads();
-    if (cand && t != pj) {
-      const cpx<RG> mdf = c_neg(xj);
+    if (t == pj) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = prow[c];
+    } else if (cand) {
+      if (t == p)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[c] = xchg[c];
+      cpx<RG> f = x[0];
+#pragma unroll
+      for (int c = 1; c < NB; ++c)
+        if (c == j) f = x[c];
+      const cpx<RG> mf = c_neg(f);
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const cpx<RG> base = (c == j) ? c_zero<RG>() : x[c];
-        x[c] = c_fma(mdf, prow[c], base);
+        x[c] = c_fma(mf, prow[c], base);
       }
     }
   }
-  if (cand)
+  __syncthreads();   // phys is final for this panel
+  if (cand) {
+    const int64_t row = (int64_t)phys[t] * Mp;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) X[(int64_t)t * Mp + k0 + c] = x[c];
+    for (int c = 0; c < NB; ++c) X[row + k0 + c] = x[c];
+  }
   return flags;
 }
 
-// Phases 2-4 of one block step; R rows in X (Mp or 2 Mp).
-template <class RG, int NB = PanelW<RG>::NB>
-__device__ void gj_block_update(cpx<RG> *X, int Mp, int R, int k0) {
-  constexpr int NBLK = NB / 16;
-  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int pt = k0 / NB, ntr = R / NB, ntc = Mp / NB;
-  const cpx<RG> *T = X + (int64_t)k0 * Mp + k0;         // pivot block, ld Mp
-  // 2. multipliers of the rows that were not candidates: [0, k0) and [Mp, R)
-  {
-    const int n_above = pt, n_below = (R - Mp) / NB;
-    for (int i = wave; i < n_above + n_below; i += nwaves) {
-      const int rt = i < n_above ? i : (Mp / NB) + (i - n_above);
-      CTile<RG, NBLK> acc;
-      acc.zero();
-      ctile_gemm<RG, NBLK>(acc, X + k0, Mp, rt * NB, T, Mp, 0, NB);
-      ctile_for_each<RG, NBLK>(acc, [&](int r, int c, RG &re, RG &im) {
-        X[(int64_t)(rt * NB + r) * Mp + k0 + c] = cpx<RG>{-re, -im};
-      });
-    }
+// Index map of a window of tiles: tile i starts at
+//   base1 + step * i            for i < n1
+//   base2 + step * (i - n1)     otherwise,
+// shifted past [hole, hole + hole_len) when it would start inside or after it.
+struct IdxMap {
+  int base1, n1, base2, n, hole, hole_len;
+  __device__ __forceinline__ int at(int i, int step) const {
+    int r = i < n1 ? base1 + step * i : base2 + step * (i - n1);
+    if (hole_len && r >= hole) r += hole_len;
+    return r;
   }
-  __syncthreads();
-  // 3. rank-NB update of everything outside pivot rows / panel columns
-  {
-    const int ntiles = (ntr - 1) * (ntc - 1);
-    for (int i = wave; i < ntiles; i += nwaves) {
-      int rt = i / (ntc - 1), ct = i % (ntc - 1);
-      rt += (rt >= pt);
-      ct += (ct >= pt);
-      CTile<RG, NBLK> acc;
-      cpx<RG> *C = X + (int64_t)rt * NB * Mp + ct * NB;
-      ctile_for_each<RG, NBLK>(acc, [&](int r, int c, RG &re, RG &im) {
-        cpx<RG> v = C[(int64_t)r * Mp + c];
+};
+__device__ __forceinline__ IdxMap imap(int base1, int n, int hole = 0, int hole_len = 0) {
+  return IdxMap{base1, n, 0, n, hole, hole_len};
+}
+__device__ __forceinline__ IdxMap imap2(int base1, int n1, int base2, int n) {
+  return IdxMap{base1, n1, base2, n, 0, 0};
+}
+
+// For every tile (r0 = rows.at(i), c0 = cols.at(j)) of the window:
+//   out[r, c] = (negate ? -1 : 1) * sum_k X[arow + r, acol + k] X[krow0 + k, c + bshift]  (+ out if accumulate)
+// with logical rows of X mapped through rm; out is X (rows mapped) or a plain
+// scratch matrix S with leading dimension lds.  Out of line: one body serves
+// every phase.
+template <class RG, int NBLK, int KT, int NT>
+__device__ __attribute__((noinline)) void tile_gemm_window_flat(
+    const cpx<RG> *X, cpx<RG> *S, int lds, const int *phys, int Mp, int rb1, int rn1, int rb2, int rn, int rh,
+    int rhl, int cb1, int cn1, int cb2, int cn, int ch, int chl, int K, int arow, int acol, int krow0,
+    int bshift, int flags) {
+  const RowMap rm{phys, Mp};
+  const IdxMap rows{rb1, rn1, rb2, rn, rh, rhl}, cols{cb1, cn1, cb2, cn, ch, chl};
+  const bool accumulate = flags & 1, negate = flags & 2;
+  const int l = lane_id();
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int ntot = rows.n * cols.n;
+  for (int it = wave; it < ntot; it += nwaves) {
+    const int r0 = rows.at(it / cols.n, 16 * NBLK), c0 = cols.at(it % cols.n, 16 * NBLK);
+    int64_t aoff[NBLK];
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i) aoff[i] = (int64_t)rm(arow + r0 + 16 * i + (l & 15)) * Mp + acol + (l >> 4);
+    cpx<RG> *Xw = const_cast<cpx<RG> *>(X);
+    auto dst_of = [=](int r, int c) -> cpx<RG> * {
+      return S ? S + (int64_t)(r0 + r) * lds + c0 + c : Xw + (int64_t)rm(r0 + r) * Mp + c0 + c;
+    };
+    CTile<RG, NBLK> acc;
+    if (accumulate)
+      ctile_for_each<RG, NBLK>(acc, [=](int r, int c, RG &re, RG &im) {
+        const cpx<RG> v = *dst_of(r, c);
         re = v.re;
         im = v.im;
       });
-      ctile_gemm<RG, NBLK>(acc, X + k0, Mp, rt * NB, X + (int64_t)k0 * Mp, Mp, ct * NB, NB);
-      ctile_for_each<RG, NBLK>(acc, [&](int r, int c, RG &re, RG &im) { C[(int64_t)r * Mp + c] = cpx<RG>{re, im}; });
-    }
-  }
-  __syncthreads();
-  // 4. pivot rows: X[P, c] <- T X[P, c]
-  {
-    for (int i = wave; i < ntc - 1; i += nwaves) {
-      const int ct = i + (i >= pt);
-      CTile<RG, NBLK> acc;
+    else
       acc.zero();
-      ctile_gemm<RG, NBLK>(acc, T, Mp, 0, X + (int64_t)k0 * Mp, Mp, ct * NB, NB);
-      ctile_for_each<RG, NBLK>(acc, [&](int r, int c, RG &re, RG &im) {
-        X[(int64_t)(k0 + r) * Mp + ct * NB + c] = cpx<RG>{re, im};
-      });
+    // operands in double-buffered chunks of CH k-slices: the loads of chunk
+    // c + 1 are in flight while the MFMAs of chunk c run
+    constexpr int CH = NBLK == 1 ? 4 : 2, NCH = KT / 4 / CH;
+    cpx<RG> a[2][CH][NBLK], b[2][CH][NBLK];
+    auto load = [&](int ch, int buf) {
+#pragma unroll
+      for (int q2 = 0; q2 < CH; ++q2) {
+        const int ks = ch * CH + q2;
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) a[buf][q2][i] = X[aoff[i] + 4 * ks];
+        const int64_t brow = (int64_t)rm(krow0 + 4 * ks + (l >> 4)) * Mp + c0 + bshift + (l & 15);
+#pragma unroll
+        for (int jb = 0; jb < NBLK; ++jb) b[buf][q2][jb] = X[brow + 16 * jb];
+      }
+    };
+    load(0, 0);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (ch + 1 < NCH) load(ch + 1, (ch + 1) & 1);
+#pragma unroll
+      for (int q2 = 0; q2 < CH; ++q2) ctile_mma<RG, NBLK>(acc, a[ch & 1][q2], b[ch & 1][q2]);
     }
+    ctile_for_each<RG, NBLK>(acc, [=](int r, int c, RG &re, RG &im) {
+      *dst_of(r, c) = negate ? cpx<RG>{-re, -im} : cpx<RG>{re, im};
+    });
   }
-  __syncthreads();
 }
 
-template <class RG, int NB = PanelW<RG>::NB>
-__device__ int gj_blocked(cpx<RG> *X, int Mp, int R, int *q, cpx<RG> *xchg, cpx<RG> *prow, double *sv,
-                          int *si) {
-  for (int i = threadIdx.x; i < Mp; i += blockDim.x) q[i] = i;
+template <class RG, int NBLK, int NT>
+__device__ __forceinline__ void tile_gemm_window(const cpx<RG> *X, cpx<RG> *S, int lds, RowMap rm, IdxMap rows,
+                                                 IdxMap cols, int K, int arow, int acol, int krow0, int bshift,
+                                                 bool accumulate, bool negate) {
+  const int fl = (accumulate ? 1 : 0) | (negate ? 2 : 0);
+#define KNIT_TGW(KT)                                                                                              \
+  tile_gemm_window_flat<RG, NBLK, KT, NT>(X, S, lds, rm.phys, rm.Mp, rows.base1, rows.n1, rows.base2, rows.n,        \
+                                      rows.hole, rows.hole_len, cols.base1, cols.n1, cols.base2, cols.n,         \
+                                      cols.hole, cols.hole_len, K, arow, acol, krow0, bshift, fl)
+  if (NBLK == 1) KNIT_TGW(16);            // inner panels: K = 16
+  else if (K == 64) KNIT_TGW(64);         // outer panels
+  else KNIT_TGW(32);                      // last outer panel of a 32-padded slice
+#undef KNIT_TGW
+}
+
+// Gauss-Jordan with partial pivoting in two levels: outer panels of NO columns
+// (NO = 64, the last one may be 32 wide) whose restricted elimination runs as
+// NI = PanelW steps confined to the outer panel's columns and to the logical
+// rows [K0, Mp); then one rank-NO update of the rest of the matrix.  The whole
+// matrix is touched once per outer panel instead of once per inner panel.
+// Sb ([R][NO]) and Sd ([NO][Mp]) hold the two products that cannot be formed
+// in place.  phys (LDS, Mp entries) receives the final row order.
+template <class RG, int NT, int NI = PanelW<RG>::NB>
+__device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg, cpx<RG> *prow, double *sv,
+                            int *si, cpx<RG> *Sb, cpx<RG> *Sd) {
+  constexpr int NO = 64;
+  constexpr int BI = NI / 16;      // inner tile blocks
+  for (int i = threadIdx.x; i < Mp; i += blockDim.x) phys[i] = i;
   __syncthreads();
+  const RowMap rm{phys, Mp};
   int flags = 0;
-  for (int k0 = 0; k0 < Mp; k0 += NB) {
-    flags |= gj_panel<RG>(X, Mp, k0, q, xchg, prow, sv, si);
+  for (int K0 = 0; K0 < Mp; K0 += NO) {
+    const int NOe = Mp - K0 < NO ? Mp - K0 : NO;
+    // ---- restricted elimination of the outer panel
+    for (int k0 = K0; k0 < K0 + NOe; k0 += NI) {
+      flags |= gj_panel<RG, NI>(X, Mp, k0, phys, xchg, prow, sv, si);
+      __syncthreads();
+      const int npan = NOe / NI, pi = (k0 - K0) / NI;
+      const IdxMap pcols = imap(K0, npan - 1, k0, NI);   // outer-panel columns minus the inner panel
+      // multipliers of the earlier pivot rows of this outer panel: rows [K0, k0)
+      if (pi > 0)
+        tile_gemm_window<RG, BI, NT>(X, nullptr, 0, rm, imap(K0, pi), imap(k0, 1), NI, 0, k0, k0, 0, false, true);
+      __syncthreads();
+      // update inside the outer panel: rows [K0, Mp) minus the pivot rows
+      if (npan > 1)
+        tile_gemm_window<RG, BI, NT>(X, nullptr, 0, rm, imap(K0, (Mp - K0) / NI - 1, k0, NI), pcols, NI, 0, k0, k0, 0,
+                                 true, false);
+      // pivot rows across the outer panel (into Sd: in place would race)
+      if (npan > 1)
+        tile_gemm_window<RG, BI, NT>(X, Sd, Mp, rm, imap(0, 1), pcols, NI, k0, k0, k0, 0, false, false);
+      __syncthreads();
+      for (int e = threadIdx.x; e < NI * NOe; e += blockDim.x) {
+        const int r = e / NOe, c = K0 + e % NOe;
+        if (c >= k0 && c < k0 + NI) continue;
+        X[(int64_t)phys[k0 + r] * Mp + c] = Sd[(int64_t)r * Mp + c];
+      }
+      __syncthreads();
+    }
+    if (NOe == Mp && R == Mp) continue;
+    // ---- rank-NO update of the rest
+    const int n_above = K0 / 32, n_below = (R - Mp) / 32;
+    const IdxMap ocols = imap(0, (Mp - NOe) / 32, K0, NOe);
+    // (b) multipliers of the rows outside [K0, Mp): Sb = -X[r, K] T
+    if (n_above + n_below > 0)
+      tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap2(0, n_above, Mp, n_above + n_below), imap(0, NOe / 32), NOe, 0,
+                              K0, K0, K0, false, true);
+    // (d) new pivot rows: Sd = T X[P, c] for c outside the panel
+    if (Mp > NOe)
+      tile_gemm_window<RG, 2, NT>(X, Sd, Mp, rm, imap(0, NOe / 32), ocols, NOe, K0, K0, K0, 0, false, false);
     __syncthreads();
-    gj_block_update<RG>(X, Mp, R, k0);
+    for (int e = threadIdx.x; e < (n_above + n_below) * 32 * NOe; e += blockDim.x) {
+      const int rr = e / NOe, c = e % NOe;
+      const int r = rr < n_above * 32 ? rr : Mp + (rr - n_above * 32);
+      X[(int64_t)rm(r) * Mp + K0 + c] = Sb[(int64_t)r * NO + c];
+    }
+    __syncthreads();
+    // (c) X[r, c] += X[r, K] X[P, c] (old pivot rows) for r outside P, c outside K
+    if (Mp > NOe)
+      tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, imap(0, R / 32 - NOe / 32, K0, NOe), ocols, NOe, 0, K0, K0, 0, true,
+                              false);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NOe * Mp; e += blockDim.x) {
+      const int r = e / Mp, c = e % Mp;
+      if (c >= K0 && c < K0 + NOe) continue;
+      X[(int64_t)phys[K0 + r] * Mp + c] = Sd[(int64_t)r * Mp + c];
+    }
+    __syncthreads();
   }
   return flags;
 }
 
-// A_n (and B_n) into X (type RG, padded), from g_{n-1}, G_{1,n-1} (type RS, natural order).
-// With REFINE also writes A_n in FP64 to A64.
-template <class RG, class RS, bool REFINE>
-__device__ void form_padded(cpx<RG> *X, cpx<double> *A64, const StripDev &s, int Mp, double E,
-                            const knit_z *D, const knit_z *sL, const knit_z *sR, bool first, bool last,
-                            const cpx<RS> *g, const cpx<RS> *G1) {
-  const int M = s.M, no = s.norb;
+// A_n (and B_n = -G_{1,n-1} V^+) into X (type RG, padded to Mp with an
+// identity block), one norb x norb site block per thread.  gprev(r, c) and
+// G1prev(r, c) return g_{n-1} and G_{1,n-1} in natural order; with REFINE
+// A_n is also written in FP64 to A64.
+template <int no, class RG, bool REFINE, class GAcc, class G1Acc>
+__device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, StripDev s, int Mp,
+                                                        double E, const knit_z *D, const knit_z *sL,
+                                                        const knit_z *sR, bool first, bool last, GAcc gprev,
+                                                        G1Acc G1prev) {
+  const int M = s.M, W = M / no, Wp = Mp / no;
   const int64_t E2 = (int64_t)Mp * Mp;
-  for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) {
-    const int a = (int)(i / Mp), b = (int)(i % Mp);
-    cpx<double> v;
-    if (a < M && b < M) {
-      const int sa = a / no, oa = a % no, sb = b / no, ob = b % no;
-      cpx<double> h = ld_z(s.H0 + (int64_t)a * M + b);
-      if (sa == sb) {
-        cpx<double> d = ld_z(D + ((int64_t)sa * no + oa) * no + ob);
-        h.re += d.re;
-        h.im += d.im;
-      }
-      if (first) {
-        cpx<double> x = ld_z(sL + (int64_t)a * M + b);
-        h.re += x.re;
-        h.im += x.im;
-      }
-      if (last) {
-        cpx<double> x = ld_z(sR + (int64_t)a * M + b);
-        h.re += x.re;
-        h.im += x.im;
-      }
-      v = {(a == b ? E : 0.0) - h.re, -h.im};
-      if (!first) {
-        const int ca = s.vcol[sa], cb = s.vcol[sb];
-        if (ca >= 0 && cb >= 0) {
+  // top: site blocks (sa, sb), one output row oa at a time
+  for (int blk = threadIdx.x; blk < Wp * Wp; blk += blockDim.x) {
+    const int sa = blk / Wp, sb = blk % Wp;
+    const bool real = sa < W && sb < W;
+    const int ca = real ? s.vcol[sa] : -1, cb = real ? s.vcol[sb] : -1;
+    const bool vgv = !first && ca >= 0 && cb >= 0;
+    cpx<double> gb[no][no];
+    if (vgv)
+#pragma unroll
+      for (int i = 0; i < no; ++i)
+#pragma unroll
+        for (int j = 0; j < no; ++j) gb[i][j] = gprev(ca * no + i, cb * no + j);
+#pragma unroll
+    for (int oa = 0; oa < no; ++oa) {
+      cpx<double> u[no];          // row oa of v_a g
+      if (vgv)
+#pragma unroll
+        for (int j = 0; j < no; ++j) {
           cpx<double> acc = {0.0, 0.0};
-          for (int ii = 0; ii < no; ++ii) {
-            cpx<double> va = vblk_at(s, sa, oa, ii);
-            cpx<double> inner = {0.0, 0.0};
-            for (int jj = 0; jj < no; ++jj)
-              inner = c_fma(cvt<double>(g[(int64_t)(ca * no + ii) * Mp + cb * no + jj]),
-                            c_conj(vblk_at(s, sb, ob, jj)), inner);
-            acc = c_fma(va, inner, acc);
-          }
-          v = c_sub(v, acc);
+#pragma unroll
+          for (int i = 0; i < no; ++i) acc = c_fma(vblk_at(s, sa, oa, i), gb[i][j], acc);
+          u[j] = acc;
         }
+#pragma unroll
+      for (int ob = 0; ob < no; ++ob) {
+        cpx<double> out;
+        if (real) {
+          const int64_t e = (int64_t)(sa * no + oa) * M + sb * no + ob;
+          cpx<double> h = ld_z(s.H0 + e);
+          if (sa == sb) {
+            const cpx<double> d = ld_z(D + ((int64_t)sa * no + oa) * no + ob);
+            h.re += d.re;
+            h.im += d.im;
+          }
+          if (first) {
+            const cpx<double> x = ld_z(sL + e);
+            h.re += x.re;
+            h.im += x.im;
+          }
+          if (last) {
+            const cpx<double> x = ld_z(sR + e);
+            h.re += x.re;
+            h.im += x.im;
+          }
+          if (vgv) {
+            cpx<double> acc = {0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < no; ++j) acc = c_fma(u[j], c_conj(vblk_at(s, sb, ob, j)), acc);
+            h.re += acc.re;
+            h.im += acc.im;
+          }
+          out = {(sa == sb && oa == ob ? E : 0.0) - h.re, -h.im};
+        } else {
+          out = {(sa == sb && oa == ob) ? 1.0 : 0.0, 0.0};
+        }
+        const int64_t o = (int64_t)(sa * no + oa) * Mp + sb * no + ob;
+        X[o] = cvt<RG>(out);
+        if (REFINE) A64[o] = out;
       }
-    } else {
-      v = {a == b ? 1.0 : 0.0, 0.0};
     }
-    X[i] = cvt<RG>(v);
-    if (REFINE) A64[i] = v;
-    if (!first) {
+  }
+  if (first) return;
+  // bottom: row a, site block sb: -(G_{1,n-1} V^+)[a, sb]
+  for (int blk = threadIdx.x; blk < Mp * Wp; blk += blockDim.x) {
+    const int a = blk / Wp, sb = blk % Wp;
+    const int cb = (sb < W && a < M) ? s.vcol[sb] : -1;
+    cpx<double> gr[no];
+    if (cb >= 0)
+#pragma unroll
+      for (int j = 0; j < no; ++j) gr[j] = G1prev(a, cb * no + j);
+#pragma unroll
+    for (int ob = 0; ob < no; ++ob) {
       cpx<double> w = {0.0, 0.0};
-      if (a < M && b < M) {
-        const int sb = b / no, ob = b % no, cb = s.vcol[sb];
-        if (cb >= 0)
-          for (int jj = 0; jj < no; ++jj)
-            w = c_fma(cvt<double>(G1[(int64_t)a * Mp + cb * no + jj]), c_conj(vblk_at(s, sb, ob, jj)), w);
-      }
-      X[E2 + i] = cvt<RG>(cpx<double>{-w.re, -w.im});
+      if (cb >= 0)
+#pragma unroll
+        for (int j = 0; j < no; ++j) w = c_fma(gr[j], c_conj(vblk_at(s, sb, ob, j)), w);
+      X[E2 + (int64_t)a * Mp + sb * no + ob] = cvt<RG>(cpx<double>{-w.re, -w.im});
     }
+  }
+}
+
+template <class RG, bool REFINE, class GAcc, class G1Acc>
+__device__ void form_blocks(cpx<RG> *X, cpx<double> *A64, const StripDev &s, int Mp, double E,
+                            const knit_z *D, const knit_z *sL, const knit_z *sR, bool first, bool last,
+                            GAcc gprev, G1Acc G1prev) {
+  switch (s.norb) {
+    case 1: form_blocks_n<1, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    case 2: form_blocks_n<2, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    default: form_blocks_n<4, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
   }
 }
 
@@ -296,32 +449,34 @@ __device__ void gather_vg(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int 
 
 __global__ void reset_queue_kernel(unsigned int *counter) { *counter = 0u; }
 
-template <class RG, class RS, bool REFINE>
-__global__ void __launch_bounds__(NT2) sweep_mfma_kernel(StripTable tab, const knit_problem *probs, int P,
-                                                         const knit_z *onsite, const knit_z *sigmaL,
-                                                         const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
-                                                         knit_z *GNN, int32_t *pstatus, char *ws,
-                                                         size_t slab_bytes, int Mpmax,
-                                                         unsigned int *queue) {
+template <class RG, class RS, bool REFINE, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sweep_mfma_kernel(StripTable tab, const knit_problem *probs, int P,
+                                                        const knit_z *onsite, const knit_z *sigmaL,
+                                                        const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
+                                                        knit_z *GNN, int32_t *pstatus, char *ws,
+                                                        size_t slab_bytes, int Mpmax, unsigned int *queue) {
   __shared__ int next_p;
-  __shared__ int q[NT2];
-  __shared__ int pinv[NT2];
-  __shared__ double sv[16];
-  __shared__ int si[16];
+  __shared__ int qa[NT], qb[NT];        // row order of the current / previous elimination
+  __shared__ int pa[NT], pb[NT];        // and its inverse (column order of the inverse)
+  __shared__ double sv[32];
+  __shared__ int si[64];
   __shared__ cpx<RG> xchg[2 * 32];
   __shared__ cpx<RG> prow[32];
 
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t EE = (int64_t)Mpmax * Mpmax;
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
-  cpx<RG> *X = reinterpret_cast<cpx<RG> *>(slab);                 // [2 Mp][Mp]
-  cpx<RS> *g = reinterpret_cast<cpx<RS> *>(X + 2 * EE);           // [Mp][Mp]
+  cpx<RG> *Xa = reinterpret_cast<cpx<RG> *>(slab);                // [2 Mp][Mp]
+  cpx<RG> *Xb = Xa + 2 * EE;                                       // [2 Mp][Mp]
+  cpx<RS> *g = reinterpret_cast<cpx<RS> *>(Xb + 2 * EE);          // [Mp][Mp]  natural order (refine / G_n1)
   cpx<RS> *G1 = g + EE;                                           // [Mp][Mp]
   cpx<RS> *N1a = G1 + EE;                                         // [Mp][Mp]
   cpx<RS> *N1b = N1a + EE;                                        // [Mp][Mp]
   cpx<double> *A64 = reinterpret_cast<cpx<double> *>(N1b + EE);   // [Mp][Mp]   (REFINE)
   cpx<float> *Xn = reinterpret_cast<cpx<float> *>(A64 + (REFINE ? EE : 0));   // [2 Mp][Mp] (REFINE)
   cpx<float> *Rr = Xn + (REFINE ? 2 * EE : 0);                    // [Mp][Mp]   (REFINE)
+  cpx<RG> *Sb = reinterpret_cast<cpx<RG> *>(Rr + (REFINE ? EE : 0));   // [2 Mp][64] scratch
+  cpx<RG> *Sd = Sb + (int64_t)2 * Mpmax * 64;                           // [64][Mp]   scratch
   const bool want_n1 = GN1 != nullptr;
   const double qnan = __builtin_nan("");
 
@@ -340,27 +495,36 @@ __global__ void __launch_bounds__(NT2) sweep_mfma_kernel(StripTable tab, const k
     const int64_t E2 = (int64_t)Mp * Mp;
     const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
     int flags = 0;
+    int *q = qa, *pinv = pa, *qp = qb, *pinvp = pb;
+    cpx<RG> *X = Xa, *Xp = Xb;
     for (int n = 0; n < L; ++n) {
       const knit_z *D = onsite + pr.onsite_off + (int64_t)n * M * no;
-      form_padded<RG, RS, REFINE>(X, A64, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1, g, G1);
+      if (REFINE || n == 0) {
+        form_blocks<RG, REFINE>(X, A64, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+                                [=](int r, int c) { return cvt<double>(g[(int64_t)r * Mp + c]); },
+                                [=](int r, int c) { return cvt<double>(G1[(int64_t)r * Mp + c]); });
+      } else {
+        // previous result in Xp: logical row r at physical row qp[r], column c of the
+        // inverse at column pinvp[c]; G_11 = g_1 is the top of slice 1's result
+        const bool top = n == 1;
+        form_blocks<RG, false>(X, A64, s, Mp, pr.E, D, sL, sR, false, n == L - 1,
+                               [=](int r, int c) { return cvt<double>(Xp[(int64_t)qp[r] * Mp + pinvp[c]]); },
+                               [=](int r, int c) {
+                                 return cvt<double>(top ? Xp[(int64_t)qp[r] * Mp + pinvp[c]]
+                                                        : Xp[(int64_t)(Mp + r) * Mp + pinvp[c]]);
+                               });
+      }
       __syncthreads();
       const int R = n > 0 ? 2 * Mp : Mp;
-      flags |= gj_blocked<RG>(X, Mp, R, q, xchg, prow, sv, si);
+      flags |= gj_two_level<RG, NT>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd);
       for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
       __syncthreads();
-      if (!REFINE) {
-        for (int64_t i = tid; i < (int64_t)R * Mp; i += nt) {
-          const int a = (int)(i / Mp), b = (int)(i % Mp);
-          cpx<RG> v = X[(int64_t)a * Mp + pinv[b]];
-          if (a < Mp) g[i] = cvt<RS>(v);
-          else G1[i - E2] = cvt<RS>(v);
-        }
-        __syncthreads();
-      } else {
+      // logical row a of the result sits in physical row q[a] (a < Mp)
+      if (REFINE) {
         // X0 (and G0) in natural column order
         for (int64_t i = tid; i < (int64_t)R * Mp; i += nt) {
           const int a = (int)(i / Mp), b = (int)(i % Mp);
-          Xn[i] = cvt<float>(X[(int64_t)a * Mp + pinv[b]]);
+          Xn[i] = cvt<float>(X[(int64_t)(a < Mp ? q[a] : a) * Mp + pinv[b]]);
         }
         __syncthreads();
         // residual R = I - A_n X0, FP64 product
@@ -376,10 +540,23 @@ __global__ void __launch_bounds__(NT2) sweep_mfma_kernel(StripTable tab, const k
           else G1[o - E2] = cvt<RS>(v);
         });
         __syncthreads();
-      }
-      if (n == 0) {
-        for (int64_t i = tid; i < E2; i += nt) G1[i] = g[i];
+        if (n == 0) {
+          for (int64_t i = tid; i < E2; i += nt) G1[i] = g[i];
+          __syncthreads();
+        }
+      } else if (want_n1 || n == L - 1) {
+        // natural-order g_n (and G_1n) when G_n1 is carried, and for the outputs
+        for (int64_t i = tid; i < (int64_t)R * Mp; i += nt) {
+          const int a = (int)(i / Mp), b = (int)(i % Mp);
+          cpx<RG> v = X[(int64_t)(a < Mp ? q[a] : a) * Mp + pinv[b]];
+          if (a < Mp) g[i] = cvt<RS>(v);
+          else G1[i - E2] = cvt<RS>(v);
+        }
         __syncthreads();
+        if (n == 0) {
+          for (int64_t i = tid; i < E2; i += nt) G1[i] = g[i];
+          __syncthreads();
+        }
       }
       if (want_n1) {
         if (n == 0) {
@@ -393,6 +570,10 @@ __global__ void __launch_bounds__(NT2) sweep_mfma_kernel(StripTable tab, const k
         }
         __syncthreads();
       }
+      // the result of this slice becomes the previous one
+      int *t1 = q; q = qp; qp = t1;
+      int *t2 = pinv; pinv = pinvp; pinvp = t2;
+      cpx<RG> *t3 = X; X = Xp; Xp = t3;
     }
     // outputs (the leading M x M blocks)
     double bad = 0.0;
@@ -404,7 +585,6 @@ __global__ void __launch_bounds__(NT2) sweep_mfma_kernel(StripTable tab, const k
       if (GNN) bad = fmax(bad, c_abs1(g[o]));
       if (want_n1) bad = fmax(bad, c_abs1(N1a[o]));
     }
-    // workgroup max over 8 waves
     if (bad != bad) bad = INFINITY;
     for (int off = 32; off > 0; off >>= 1) bad = fmax(bad, __shfl_xor(bad, off, 64));
     if ((tid & 63) == 0) sv[tid >> 6] = bad;
@@ -434,14 +614,16 @@ int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
 size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
   const size_t Mp = (size_t)mfma_padded(Mmax);
   const size_t EE = Mp * Mp;
+  const size_t gs = precision == KNIT_FP64 ? 16 : 8;     // elimination element size
   size_t b;
-  if (precision == KNIT_FP64) b = EE * (2 * 16 + 4 * 16);
-  else if (precision == KNIT_FP32) b = EE * (2 * 8 + 4 * 8);
-  else b = EE * (2 * 8 + 4 * 16 + 16 + 2 * 8 + 8);
+  if (precision == KNIT_FP64) b = EE * (4 * 16 + 4 * 16);
+  else if (precision == KNIT_FP32) b = EE * (4 * 8 + 4 * 8);
+  else b = EE * (4 * 8 + 4 * 16 + 16 + 2 * 8 + 8);
+  b += (2 * Mp * 64 + 64 * Mp) * gs;                      // Sb, Sd scratch
   return (b + 255) & ~size_t(255);
 }
 
-bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= NT2; }
+bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= 512; }
 
 // Workspace: a 256-byte header (queue counter) then one slab per workgroup.
 size_t sweep_mfma_workspace(int Mmax, int precision, int P) {
@@ -457,24 +639,29 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
   char *w = reinterpret_cast<char *>(ws) + 256;
   const size_t slab = sweep_mfma_slab_bytes(Mmax, precision);
   const int Mpmax = mfma_padded(Mmax);
-  // one resident workgroup per compute unit (8 waves of up to 256 VGPRs)
+  // workgroup of 256 threads (two resident per compute unit) when the padded
+  // slice fits one panel row per thread, else 512
+  const bool small = Mpmax <= 256;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  int grid = ncu < SWEEP_MAX_GRID ? ncu : SWEEP_MAX_GRID;
+  int grid = small ? 2 * ncu : ncu;
+  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
   if (grid > P) grid = P;
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, queue);
-  if (precision == KNIT_FP64)
-    hipLaunchKernelGGL((sweep_mfma_kernel<double, double, false>), dim3(grid), dim3(NT2), 0, stream, tab,
-                       probs, P, onsite, sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue);
-  else if (precision == KNIT_FP32)
-    hipLaunchKernelGGL((sweep_mfma_kernel<float, float, false>), dim3(grid), dim3(NT2), 0, stream, tab,
-                       probs, P, onsite, sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue);
-  else
-    hipLaunchKernelGGL((sweep_mfma_kernel<float, double, true>), dim3(grid), dim3(NT2), 0, stream, tab,
-                       probs, P, onsite, sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue);
+#define KNIT_LAUNCH(RG, RS, RF, NT)                                                                          \
+  hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, \
+                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue)
+  if (precision == KNIT_FP64) {
+    if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
+  } else if (precision == KNIT_FP32) {
+    if (small) KNIT_LAUNCH(float, float, false, 256); else KNIT_LAUNCH(float, float, false, 512);
+  } else {
+    if (small) KNIT_LAUNCH(float, double, true, 256); else KNIT_LAUNCH(float, double, true, 512);
+  }
+#undef KNIT_LAUNCH
   return hipGetLastError();
 }
 
