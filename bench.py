@@ -1,15 +1,20 @@
 """Benchmark of the two-lead strip transport path on one MI355X.
 
-One step = the whole T(E) path over the batch, inputs resident in HBM:
-lead self-energies of both leads for every energy (double-double decimation),
-the slice sweep of every (energy, realization) problem, and the Fisher-Lee
-trace.  The headline precision is the FP32 matrix-core sweep with one
-FP64-residual refinement per slice inverse; the FP64 sweep is timed beside it
-on the same batch, and every mixed-precision T(E) is compared with the FP64
-one per open channel.
+One step = the whole T(E) path over the batch, with the inputs resident in HBM:
+  * the lead self-energies of both leads for every energy (double-double
+    decimation);
+  * the slice sweep of every (energy, realization) problem;
+  * the Fisher-Lee trace.
 
-Prints one JSON line (see the fields below).  --gpus above 1 is refused: this
-build runs on one GPU.
+Both precisions are timed over a full step:
+  * the FP64 matrix-core sweep;
+  * the FP32 matrix-core sweep with one FP64-residual refinement per slice
+    inverse.
+Every mixed-precision T(E) is compared with the FP64 one, per open channel.
+The headline `value` is the step throughput of the path whose T(E) meets the
+tolerance on every point. The other path's figures sit beside it.
+
+Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
 
 from __future__ import annotations
@@ -29,21 +34,28 @@ if ROOT not in sys.path:
 METRIC = "RGF slice-steps/s at W=256, FP32-MFMA+refine vs FP64; T(E) points/s at |ΔT|≤1e-6"
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32_refine": 157.3}
+TOL_PER_CHANNEL = 1e-6
 
 WORKLOADS = {
-    # name: (builder kwargs, description)
+    # name: builder kwargs and description
+    "c4": dict(kind="rashba", W=256, L=512, w=2.0, n_energies=64, n_seeds=8,
+               desc="spinful square lattice W=256 (slice dim M=512), Rashba 0.2t, Zeeman 0.1t (sigma_z), "
+                    "L=512, disorder U[-1,1] sigma0, 64 midpoint energies in (-3.9,3.9) x 8 seeds "
+                    "= 512 problems"),
     "c2": dict(kind="square", W=128, L=1024, w=2.0, n_energies=256, n_seeds=16,
                desc="square-lattice strip W=128 (M=128), L=1024, disorder U[-1,1], "
                     "256 midpoint energies in (-3.9,3.9) x 16 seeds = 4096 problems"),
     "c2w256": dict(kind="square", W=256, L=1024, w=2.0, n_energies=64, n_seeds=8,
                    desc="square-lattice strip W=256 (M=256), L=1024, disorder U[-1,1], "
                         "64 energies x 8 seeds = 512 problems"),
-    "c4": dict(kind="rashba", W=256, L=512, w=2.0, n_energies=64, n_seeds=8,
-               desc="spinful square lattice W=256 (M=512), Rashba 0.2t, Zeeman 0.1t, L=512, "
-                    "disorder U[-1,1], 64 energies x 8 seeds = 512 problems"),
     "c1": dict(kind="square", W=16, L=64, w=1.0, n_energies=64, n_seeds=1,
                desc="square-lattice strip W=16, L=64, disorder U[-0.5,0.5], 64 energies"),
 }
+
+
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def build_batch(cfg):
@@ -53,24 +65,30 @@ def build_batch(cfg):
     return workload.rashba_batch(cfg["W"], cfg["L"], cfg["w"], cfg["n_energies"], cfg["n_seeds"])
 
 
-def open_channels(cfg, energies):
-    """N_open(E) of the lead = transmission of the clean strip (one slice), on the GPU path."""
+def open_channels(cfg, b):
+    """N_open(E) of the lead: T of the clean strip (one slice between the two leads), GPU path,
+    with the batch's own self-energies."""
     import torch
     from paper_1010_2627_amd import workload
     if cfg["kind"] == "square":
-        b = workload.square_batch(cfg["W"], 1, 0.0, 1, 1)
+        c = workload.square_batch(cfg["W"], 1, 0.0, 1, 1)
     else:
-        b = workload.rashba_batch(cfg["W"], 1, 0.0, 1, 1)
-    b = workload.Batch(b.strips, b.realizations, [np.asarray(energies)])
-    b.compute_sigmas()
-    G1N, _, _, st = b.sweep("fp64", gnn=False)
-    T = b.transmission(G1N)[0]
+        c = workload.rashba_batch(cfg["W"], 1, 0.0, 1, 1)
+    c = workload.Batch(c.strips, c.realizations, [np.asarray(b.energies[0])])
+    c.sigmaL, c.sigmaR = b.sigmaL, b.sigmaR
+    G1N, _, _, _ = c.sweep("fp64", gnn=False)
+    T = c.transmission(G1N)[0]
     torch.cuda.synchronize()
     return np.rint(T.cpu().numpy()).astype(np.int64)
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The CPU oracle on a bounded sample of the same workload (oracle untuned)."""
+def cpu_baseline(cfg, b, budget_s=20.0):
+    """The CPU oracle on a bounded sample of the same workload (oracle untuned).
+
+    Up to M = 256 the sample includes the oracle's own lead self-energies (Bloch-mode
+    method).  Above that one such solve takes about a minute per energy, so the sample
+    times the oracle's sweep and trace only, fed with the batch's self-energies, and the
+    rate is compared with the GPU sweep rate."""
     from paper_1010_2627_amd import inputs
     from oracle import leads as OL
     from oracle import rgf as OR
@@ -79,20 +97,27 @@ def cpu_baseline(cfg, budget_s=20.0):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:                                                  # pragma: no cover
         threads = os.cpu_count() or 1
-    st = inputs.square_strip(cfg["W"]) if cfg["kind"] == "square" else inputs.rashba_strip(cfg["W"])
+    st = b.strips[0]
     V = st.V_dense()
-    E_all = inputs.midpoint_grid(-3.9, 3.9, cfg["n_energies"])
-    nE = 4
-    E = E_all[np.linspace(0, len(E_all) - 1, nE).astype(int)]
-    on = inputs.onsite_disorder(st, cfg["L"], cfg["w"], inputs.SEED_BASE)
-    # bounded number of slices so the sample stays within the time budget
+    E_all = np.asarray(b.energies[0])
+    nE = 4 if st.M <= 256 else 2
+    idx = np.linspace(0, len(E_all) - 1, nE).astype(int)
+    E = E_all[idx]
+    on = b.realizations[0].onsite
+    L = on.shape[0]
+    with_sigma = st.M <= 256
     t0 = time.perf_counter()
-    sL = np.stack([OL.sigma_modes(st.H0, V, e, "L") for e in E])
-    sR = np.stack([OL.sigma_modes(st.H0, V, e, "R") for e in E])
-    t_sigma = time.perf_counter() - t0
-    L = cfg["L"]
+    if with_sigma:
+        sL = np.stack([OL.sigma_modes(st.H0, V, e, "L") for e in E])
+        sR = np.stack([OL.sigma_modes(st.H0, V, e, "R") for e in E])
+    else:
+        M = st.M
+        sL = np.stack([b.sigmaL[int(i) * M * M:(int(i) + 1) * M * M].view(M, M).cpu().numpy() for i in idx])
+        sR = np.stack([b.sigmaR[int(i) * M * M:(int(i) + 1) * M * M].view(M, M).cpu().numpy() for i in idx])
+    t_sigma = time.perf_counter() - t0 if with_sigma else 0.0
+    # a bounded number of slices keeps the sample inside the time budget
     t1 = time.perf_counter()
-    probe = max(4, min(L, 32))
+    probe = max(4, min(L, 16))
     OR.rgf_forward(st.H0, V, on[:probe], E, sL, sR)
     per_slice = (time.perf_counter() - t1) / probe
     Ls = int(max(probe, min(L, (budget_s - t_sigma) / max(per_slice, 1e-9))))
@@ -101,25 +126,29 @@ def cpu_baseline(cfg, budget_s=20.0):
     OR.transmission_lr(sL, sR, r["G1N"])
     t_sweep = time.perf_counter() - t2
     steps = nE * Ls
+    what = (f"lead self-energies by the oracle's Bloch-mode method ({t_sigma:.1f} s, pro-rated to "
+            f"{Ls}/{L} of the strip), sweep and trace {t_sweep:.1f} s" if with_sigma else
+            f"sweep and trace only ({t_sweep:.1f} s; compare with sweep_slice_steps_per_s): one "
+            f"Bloch-mode self-energy at M={st.M} takes about a minute per energy on the host")
     return {"value": steps / (t_sigma * Ls / L + t_sweep), "unit": "slice-steps/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{nE} energies x 1 seed of this workload, first {Ls} of {L} slices; "
-                      f"lead self-energies by the Bloch-mode method ({t_sigma:.1f} s, pro-rated to "
-                      f"{Ls}/{L} of the strip), sweep {t_sweep:.1f} s"}
+            "sample": f"{nE} energies x 1 seed of this workload, first {Ls} of {L} slices; {what}"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32_refine", choices=["fp32_refine", "fp32", "fp64"])
-    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device copy of this size (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
+                                   "is described, not run)"}))
         sys.exit(2)
 
     import torch
@@ -127,22 +156,34 @@ def main():
 
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     b = build_batch(cfg)
     M = b.strips[0].M
     steps_per_pass = b.slice_steps()
     flops_per_pass = 16.0 * M ** 3 * steps_per_pass
-    ws = torch.empty(max(knit.knit_rgf_sweep_workspace(b.dstrips, b.probs, args.precision), 1),
-                     dtype=torch.uint8, device="cuda")
     G1N = torch.empty(b.P * M * M, dtype=torch.complex128, device="cuda")
     stream = torch.cuda.current_stream()
+    wss = {}
 
-    def one_step(prec=args.precision, events=None):
+    def ws_for(prec):
+        if prec not in wss:
+            wss[prec] = torch.empty(max(knit.knit_rgf_sweep_workspace(b.dstrips, b.probs, prec), 1),
+                                    dtype=torch.uint8, device="cuda")
+        return wss[prec]
+
+    def one_step(prec, events=None):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record(stream)
         b.compute_sigmas()
         e[1].record(stream)
         _, _, _, status = knit.knit_rgf_sweep(b.dstrips, b.probs, b.onsite, b.sigmaL, b.sigmaR, prec,
-                                              G1N=G1N, workspace=ws)
+                                              G1N=G1N, workspace=ws_for(prec))
         e[2].record(stream)
         T = b.transmission(G1N)[0]
         e[3].record(stream)
@@ -150,76 +191,80 @@ def main():
             events.append(e)
         return T, status
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    evs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        T, status = one_step(events=evs)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / args.steps
-    ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in evs]) / 1e3
-    t_sigma, t_sweep, t_trace = ph.mean(axis=0)
-    T_mixed = T.cpu().numpy()
-    bad_status = int((status.cpu().numpy() != 0).sum()) + int((b.sigma_status.cpu().numpy() != 0).sum())
+    def timed(prec, steps):
+        evs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            T, status = one_step(prec, evs)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                       for e in evs]) / 1e3
+        bad = int((status.cpu().numpy() != 0).sum()) + int((b.sigma_status.cpu().numpy() != 0).sum())
+        return T.cpu().numpy(), wall, ph.mean(axis=0), bad
 
-    extra = {}
-    if not args.no_fp64_compare and args.precision != "fp64":
-        ws64 = torch.empty(max(knit.knit_rgf_sweep_workspace(b.dstrips, b.probs, "fp64"), 1),
-                           dtype=torch.uint8, device="cuda")
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        knit.knit_rgf_sweep(b.dstrips, b.probs, b.onsite, b.sigmaL, b.sigmaR, "fp64", G1N=G1N, workspace=ws64)
-        e0.record(stream)
-        knit.knit_rgf_sweep(b.dstrips, b.probs, b.onsite, b.sigmaL, b.sigmaR, "fp64", G1N=G1N, workspace=ws64)
-        e1.record(stream)
-        T64 = b.transmission(G1N)[0].cpu().numpy()
-        t64 = e0.elapsed_time(e1) / 1e3
-        del ws64
-        nopen = open_channels(cfg, b.energies[0])
-        nopen_p = np.tile(nopen, len(b.realizations))
-        dT = np.abs(T_mixed - T64)
-        rel = dT / np.maximum(1, nopen_p)
-        ok = rel <= 1e-6
-        extra = {
-            "fp64_sweep_s": round(t64, 4),
-            "fp64_slice_steps_per_s": steps_per_pass / t64,
-            "fp64_frac_of_fp64_peak": flops_per_pass / t64 / 1e12 / PEAK_TFLOPS["fp64"],
-            "mixed_over_fp64_sweep_speedup": t64 / t_sweep,
-            "max_dT_per_open_channel_vs_fp64": float(rel.max()),
-            "max_abs_dT_vs_fp64": float(dT.max()),
-            "points_within_1e-6_per_channel": int(ok.sum()),
-            "t_points_per_s": float(ok.sum()) / wall,
-        }
-    achieved = flops_per_pass / t_sweep / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    progress(f"workload {args.workload}: {b.P} problems, M={M}, {steps_per_pass} slice-steps per step")
+    for i in range(args.warmup):
+        one_step("fp64")
+        torch.cuda.synchronize()
+        progress(f"warmup step {i + 1}/{args.warmup} done")
+    T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", args.steps)
+    progress(f"fp64: {args.steps} timed step(s), {wall64:.2f} s/step (self-energies {ts64:.2f} s, "
+             f"sweep {tw64:.2f} s, trace {tt64:.3f} s)")
+    nopen = np.tile(open_channels(cfg, b), len(b.realizations))
+
+    achieved = flops_per_pass / tw64 / 1e12
     out = {
         "metric": METRIC,
-        "value": steps_per_pass / wall,
+        "value": steps_per_pass / wall64,
         "unit": "slice-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3,
+        "ms_per_step": wall64 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32_refine": "f32+f64", "fp32": "f32", "fp64": "f64"}[args.precision],
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": cfg["desc"], "slice_dim_M": M,
                    "problems": b.P, "slice_steps_per_step": steps_per_pass,
-                   "precision": args.precision},
-        "phases_s": {"lead_selfenergy_dd": round(float(t_sigma), 4), "sweep": round(float(t_sweep), 4),
-                     "trace": round(float(t_trace), 4)},
-        "sweep_slice_steps_per_s": steps_per_pass / t_sweep,
-        "problems_with_status": bad_status,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "sweep_mfma_kernel", "flops_per_slice_step": "16*M^3"},
+                   "headline_precision": "fp64 (the path meeting the T tolerance at every point)"},
+        "phases_s": {"lead_selfenergy_dd": round(float(ts64), 4), "sweep": round(float(tw64), 4),
+                     "trace": round(float(tt64), 4)},
+        "sweep_slice_steps_per_s": steps_per_pass / tw64,
+        "t_points_per_s": b.P / wall64,
+        "problems_with_status": bad64,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                     "kernel": "sweep_mfma_kernel<double> (FP64 MFMA)",
+                     "flops_per_slice_step": "16*M^3 (8M^3 inverse + 8M^3 propagator)"},
     }
-    out.update(extra)
+    if not args.no_mixed:
+        Tm, wallm, (tsm, twm, ttm), badm = timed("fp32_refine", 1)
+        progress(f"fp32_refine: {wallm:.2f} s/step (sweep {twm:.2f} s)")
+        dT = np.abs(Tm - T64)
+        rel = dT / np.maximum(1, nopen)
+        ok = rel <= TOL_PER_CHANNEL
+        am = flops_per_pass / twm / 1e12
+        out["fp32_refine"] = {
+            "slice_steps_per_s": steps_per_pass / wallm,
+            "sweep_s": round(float(twm), 4),
+            "sweep_slice_steps_per_s": steps_per_pass / twm,
+            "frac_of_fp32_peak": am / PEAK_TFLOPS["fp32_refine"],
+            "sweep_speedup_vs_fp64": tw64 / twm,
+            "max_dT_per_open_channel_vs_fp64": float(rel.max()),
+            "median_dT_per_open_channel_vs_fp64": float(np.median(rel)),
+            "max_abs_dT_vs_fp64": float(dT.max()),
+            "points_within_1e-6_per_channel": f"{int(ok.sum())}/{b.P}",
+            "t_points_per_s_within_tol": float(ok.sum()) / wallm,
+            "problems_with_status": badm,
+        }
+    out["n_open_range"] = [int(nopen.min()), int(nopen.max())]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"] = cpu_baseline(cfg, b)
+        progress("cpu baseline done")
     print(json.dumps(out))
 
 

@@ -47,6 +47,7 @@ extern "C" {
 #define KNIT_MAX_STRIPS 64     /* strip classes per batch */
 #define KNIT_MAX_M 1024        /* largest slice dimension */
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
+#define KNIT_MAX_SELFENERGY_M 512   /* largest slice for knit_lead_selfenergy */
 
 typedef struct knit_z { double re, im; } knit_z;
 
@@ -134,14 +135,20 @@ const char *knit_status_string(int code);
  * the doubling stays far below eta, then returns
  *   side 0 (left lead):  Sigma_L = V g V^+,  g = (z - H0 - V g V^+)^{-1}
  *   side 1 (right lead): Sigma_R = V^+ g V,  g = (z - H0 - V^+ g V)^{-1}
+ *   side 2 (both leads from one doubling run: the right lead's surface term is
+ *          the half of the bulk update the left run computes anyway)
  * Iteration stops when both decimated couplings fall below tol * scale
  * (scale = max(1, max|H0|, max|V|)) or after max_iter steps (KNIT_P_NOCONV).
+ * Each step's inverse (z - eps_k)^{-1} is an FP64 matrix-core inverse refined
+ * by two double-double Newton steps; M above KNIT_MAX_SELFENERGY_M returns
+ * KNIT_E_UNSUPPORTED.  The call queues max_iter steps without waiting for the
+ * device; energies that have converged skip the remaining steps.
  *
  *   strip     host   strip class
- *   side      0 = left lead, 1 = right lead
+ *   side      0 = left lead, 1 = right lead, 2 = both
  *   E         device [nE] energies
  *   eta       broadening, > 0 (1e-13 recommended)
- *   sigma     device [nE][M][M] output
+ *   sigma     device [nE][M][M] output; side 2: [2][nE][M][M], left block first
  *   iters     device [nE] output iteration counts, or NULL
  *   pstatus   device [nE] output status words
  */

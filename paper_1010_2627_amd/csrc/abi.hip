@@ -84,25 +84,26 @@ const char *knit_status_string(int code) {
 
 size_t knit_lead_selfenergy_workspace(const knit_strip *strip, int32_t nE) {
   if (!strip_ok(strip) || nE < 0) return 0;
-  return (size_t)nE * decimation_bytes_per_energy(strip->M);
+  return decimation_workspace(strip->M, nE);
 }
 
 int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E, int32_t nE,
                          double eta, double tol, int32_t max_iter, knit_z *sigma, int32_t *iters,
                          int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
   if (!strip_ok(strip)) return KNIT_E_ARG;
-  if (side != 0 && side != 1) return KNIT_E_ARG;
+  if (side < 0 || side > 2) return KNIT_E_ARG;
   if (nE < 0) return KNIT_E_ARG;
   if (!(eta > 0.0) || !isfinite(eta)) return KNIT_E_ARG;
   if (!(tol > 0.0) || !isfinite(tol)) return KNIT_E_ARG;
   if (max_iter < 1) return KNIT_E_ARG;
+  if (strip->M > KNIT_MAX_SELFENERGY_M) return KNIT_E_UNSUPPORTED;
   if (nE == 0) return KNIT_OK;
   if (!E || !sigma || !pstatus) return KNIT_E_ARG;
   const size_t need = knit_lead_selfenergy_workspace(strip, nE);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
   StripDev s{strip->M, strip->norb, strip->H0, strip->vcol, strip->vblk};
   hipError_t err = launch_decimation(s, side, E, nE, eta, tol, max_iter, sigma, iters, pstatus, ws,
-                                     decimation_bytes_per_energy(strip->M), (hipStream_t)stream);
+                                     (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 

@@ -22,176 +22,408 @@
 // must meet; with ~106-bit arithmetic the same iteration reaches eta = 1e-13
 // with rounding far below it.
 //
-// One workgroup per energy; all matrices live in this energy's workspace.
+// Both leads from one run: swapping alpha and beta leaves the doubling
+// unchanged (g_k, eps and the pair {a, b} are symmetric in the swap), so the
+// right lead's surface term b g_k a is the second half of the bulk update the
+// left run computes anyway.  With side 2 the second surface eps_r collects it.
+//
+// Work layout (every energy runs the same sequence of launches):
+//   * g_k: the FP64 inverse of z - eps_k on the matrix cores (one workgroup
+//     per energy), then two Newton steps X <- X + X (I - A X) in
+//     double-double, each of which squares the residual (1e-16 kappa -> ~1e-64
+//     kappa^4);
+//   * every product is a batched double-double tile GEMM over (tile, energy),
+//     so all compute units share the work of every energy;
+//   * convergence is decided on the device per energy: later launches skip
+//     finished energies, and the host issues max_iter iterations without
+//     waiting for the device.
 
 #include "knit_internal.h"
-#include "knit_wg.h"
 
 namespace knit {
 
 namespace {
 
-constexpr int NBUF = 13;   // eps_s, eps, a, b, a2, b2, X, ga, gb, t1, t2, Vf, Vb
+#pragma clang fp contract(off)
 
-__global__ void __launch_bounds__(WG) decimation_kernel(StripDev s, int side, const double *E, int nE,
-                                                        double eta, double tol, int max_iter,
-                                                        knit_z *sigma, int32_t *iters,
-                                                        int32_t *pstatus, char *ws,
-                                                        size_t per_energy) {
-  using C = cpx<dd>;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int e = blockIdx.x;
-  if (e >= nE) return;
-  const int M = s.M;
+using Z = cpx<dd>;
+using D = cpx<double>;
+
+constexpr int GT = 32;     // GEMM output tile edge
+constexpr int GK = 16;     // GEMM k-slice staged in LDS
+constexpr int GTHREADS = 256;
+constexpr int EW = 256;    // elementwise kernels: threads per workgroup
+constexpr int EW_BLOCKS = 64;   // elementwise kernels: workgroups per energy
+
+// Per-energy state, at the start of the workspace.
+struct DecState {
+  int32_t done, iters, flags, pad;
+  unsigned long long amax;   // bits of a non-negative double (max |a|, |b| of the step)
+  unsigned long long scale;  // bits of max(1, max |H0|, max |V|)
+};
+
+// Per-energy slab: buffer offsets in bytes.
+struct Slab {
+  size_t bytes;
+  size_t z[17];               // double-double [M][M] buffers
+  size_t x64, scr, xi64;      // FP64: padded [Mp][Mp], elimination scratch, natural [M][M]
+};
+enum { ZEPS_S, ZEPS_R, ZEPS, ZA, ZXA, ZXB, ZR, ZGA, ZGB, ZT1, ZT2, ZA0, ZA1, ZB0, ZB1, ZVF, ZVB };
+
+Slab slab_of(int M) {
+  Slab s{};
+  size_t off = 0;
+  const size_t zb = (((size_t)M * M * sizeof(Z)) + 255) & ~size_t(255);
+  for (int i = 0; i < 17; ++i) {
+    s.z[i] = off;
+    off += zb;
+  }
+  const size_t Mp = (size_t)mfma_padded(M);
+  s.x64 = off;
+  off += ((Mp * Mp * sizeof(D)) + 255) & ~size_t(255);
+  s.scr = off;
+  off += ((inverse_fp64_scratch_elems(M) * sizeof(D)) + 255) & ~size_t(255);
+  s.xi64 = off;
+  off += (((size_t)M * M * sizeof(D)) + 255) & ~size_t(255);
+  s.bytes = off;
+  return s;
+}
+
+__device__ __forceinline__ Z zdd(D v) { return {dd{v.re, 0.0}, dd{v.im, 0.0}}; }
+__device__ __forceinline__ Z zdd(Z v) { return v; }
+__device__ __forceinline__ double to_d(dd v) { return v.hi + v.lo; }
+
+// acc (hi, lo) += x * y for double-double x, y: the product's leading part is
+// added with an exact two_sum; its rounding error and the cross terms go to
+// lo, which is renormalised once after the k loop.
+__device__ __forceinline__ void dd_acc(double &hi, double &lo, dd x, dd y) {
+  const double p = x.hi * y.hi;
+  const double e = __builtin_fma(x.hi, y.hi, -p);
+  const double s = hi + p;
+  const double bb = s - hi;
+  const double t = (hi - (s - bb)) + (p - bb);
+  hi = s;
+  lo = lo + (t + e);
+  lo = __builtin_fma(x.hi, y.lo, lo);
+  lo = __builtin_fma(x.lo, y.hi, lo);
+}
+
+// C_e = cI I + (+/-) A_e B_e + [D_e], all [M][M], double-double C and D,
+// A and B double-double or FP64.  Grid: (tiles of C, energies).
+template <class TA, class TB>
+__global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB *B, const Z *Dm, Z *C,
+                                                           int64_t stride_bytes, int M, double cI,
+                                                           int negate, const DecState *st, int check_done) {
+  __shared__ Z As[GT][GK + 1];
+  __shared__ Z Bs[GK][GT + 1];
+  const int e = blockIdx.y;
+  if (check_done && st[e].done) return;
+  const int64_t eo = (int64_t)e * stride_bytes;
+  const TA *Ae = reinterpret_cast<const TA *>(reinterpret_cast<const char *>(A) + eo);
+  const TB *Be = reinterpret_cast<const TB *>(reinterpret_cast<const char *>(B) + eo);
+  Z *Ce = reinterpret_cast<Z *>(reinterpret_cast<char *>(C) + eo);
+  const Z *De = Dm ? reinterpret_cast<const Z *>(reinterpret_cast<const char *>(Dm) + eo) : nullptr;
+  const int tiles_n = (M + GT - 1) / GT;
+  const int r0 = (blockIdx.x / tiles_n) * GT, c0 = (blockIdx.x % tiles_n) * GT;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[2][2][4];   // [i][j][re.hi, re.lo, im.hi, im.lo]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.0;
+  for (int k0 = 0; k0 < M; k0 += GK) {
+    // stage A[r0:r0+32, k0:k0+16] and B[k0:k0+16, c0:c0+32], zero outside M
+    for (int i = tid; i < GT * GK; i += GTHREADS) {
+      const int r = i / GK, k = i % GK;
+      const int gr = r0 + r, gk = k0 + k;
+      As[r][k] = (gr < M && gk < M) ? zdd(Ae[(int64_t)gr * M + gk]) : Z{{0.0, 0.0}, {0.0, 0.0}};
+    }
+    for (int i = tid; i < GK * GT; i += GTHREADS) {
+      const int k = i / GT, c = i % GT;
+      const int gk = k0 + k, gc = c0 + c;
+      Bs[k][c] = (gk < M && gc < M) ? zdd(Be[(int64_t)gk * M + gc]) : Z{{0.0, 0.0}, {0.0, 0.0}};
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < GK; ++k) {
+      Z a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[ty + 16 * i][k];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const dd nai = {-a[i].im.hi, -a[i].im.lo};
+          dd_acc(acc[i][j][0], acc[i][j][1], a[i].re, b[j].re);
+          dd_acc(acc[i][j][0], acc[i][j][1], nai, b[j].im);
+          dd_acc(acc[i][j][2], acc[i][j][3], a[i].re, b[j].im);
+          dd_acc(acc[i][j][2], acc[i][j][3], a[i].im, b[j].re);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+      if (r >= M || c >= M) continue;
+      Z v = {quick_two_sum(acc[i][j][0], acc[i][j][1]), quick_two_sum(acc[i][j][2], acc[i][j][3])};
+      if (negate) v = c_neg(v);
+      if (cI != 0.0 && r == c) v.re = r_add(v.re, dd{cI, 0.0});
+      if (De) v = c_add(v, De[(int64_t)r * M + c]);
+      Ce[(int64_t)r * M + c] = v;
+    }
+}
+
+__device__ __forceinline__ char *slab_ptr(char *ws, const Slab &sl, int e, size_t off) {
+  return ws + (size_t)e * sl.bytes + off;
+}
+
+// eps_s = eps_r = eps = H0, a = alpha, b = beta, Vf = alpha, Vb = beta (dd);
+// state reset; scale = max(1, max|H0|, max|V|).
+__global__ void __launch_bounds__(EW) dec_init_kernel(StripDev s, int side, char *ws, Slab sl, DecState *st) {
+  const int e = blockIdx.y, M = s.M;
   const int64_t MM = (int64_t)M * M;
-  const int tid = threadIdx.x, nt = blockDim.x;
-
-  C *base = reinterpret_cast<C *>(ws + (size_t)e * per_energy);
-  C *eps_s = base + 0 * MM, *eps = base + 1 * MM, *a = base + 2 * MM, *b = base + 3 * MM;
-  C *a2 = base + 4 * MM, *b2 = base + 5 * MM, *X = base + 6 * MM, *ga = base + 7 * MM;
-  C *gb = base + 8 * MM, *t1 = base + 9 * MM, *t2 = base + 10 * MM;
-  C *Vf = base + 11 * MM;   // alpha as seen from the system: V (left) or V^+ (right)
-  C *Vb = base + 12 * MM;   // beta: V^+ (left) or V (right)
-
-  // LDS: GJ scratch and GEMM scratch share one region
-  int *q = reinterpret_cast<int *>(lds_raw);
-  int *pinv = q + M;
-  double *sv = reinterpret_cast<double *>(pinv + M);
-  int *si = reinterpret_cast<int *>(sv + WG / WAVE);
-  C *colj = reinterpret_cast<C *>(si + WG / WAVE + 8);
-  colj = reinterpret_cast<C *>((reinterpret_cast<uintptr_t>(colj) + 15) & ~uintptr_t(15));
-  C *prow = colj + M;
-  C *gemm_lds = colj;       // 2*32*16 entries, used only outside the GJ
-
-  const double Ez = E[e];
-  const C z = {dd{Ez, 0.0}, dd{eta, 0.0}};
+  Z *eps_s = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_S]));
+  Z *eps_r = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_R]));
+  Z *eps = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS]));
+  Z *a = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZA0]));
+  Z *b = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZB0]));
+  Z *vf = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZVF]));
+  Z *vb = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZVB]));
   double scale = 1.0;
-  for (int64_t i = tid; i < MM; i += nt) {
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < MM; i += (int64_t)gridDim.x * EW) {
     const int r = (int)(i / M), c = (int)(i % M);
-    cpx<double> h = ld_z(s.H0 + i);
-    eps_s[i] = eps[i] = C{dd{h.re, 0.0}, dd{h.im, 0.0}};
-    cpx<double> v = strip_V(s, r, c);                 // V[r][c]
-    cpx<double> vt = strip_V(s, c, r);                // V[c][r] -> (V^+)[r][c] = conj(vt)
-    C Vrc = {dd{v.re, 0.0}, dd{v.im, 0.0}};
-    C Vdrc = {dd{vt.re, 0.0}, dd{-vt.im, 0.0}};
+    const D h = ld_z(s.H0 + i);
+    eps_s[i] = eps_r[i] = eps[i] = zdd(h);
+    const D v = strip_V(s, r, c);           // V[r][c]
+    const D vt = strip_V(s, c, r);          // (V^+)[r][c] = conj(V[c][r])
+    const Z Vrc = zdd(v), Vdrc = zdd(D{vt.re, -vt.im});
     scale = fmax(scale, fmax(fabs(h.re) + fabs(h.im), fabs(v.re) + fabs(v.im)));
-    if (side == 0) {
-      a[i] = Vrc;
-      b[i] = Vdrc;
-      Vf[i] = Vrc;
-      Vb[i] = Vdrc;
+    const bool left = side != 1;
+    a[i] = vf[i] = left ? Vrc : Vdrc;
+    b[i] = vb[i] = left ? Vdrc : Vrc;
+  }
+  // scale: non-negative doubles order like their bit patterns
+  atomicMax(&st[e].scale, (unsigned long long)__double_as_longlong(scale));
+}
+
+__global__ void dec_reset_state_kernel(DecState *st, int nE) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nE) st[e] = DecState{0, 0, 0, 0, 0ull, 0ull};
+}
+
+// A = z - es (dd) and its FP64 copy, padded to Mp with an identity block.
+__global__ void __launch_bounds__(EW) dec_form_kernel(int M, int Mp, const double *E, double eta, char *ws, Slab sl,
+                                                      int src, const DecState *st, int check_done) {
+  const int e = blockIdx.y;
+  if (check_done && st[e].done) return;
+  const Z *es = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[src]));
+  Z *A = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZA]));
+  D *X64 = reinterpret_cast<D *>(slab_ptr(ws, sl, e, sl.x64));
+  const double Ez = E[e];
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)Mp * Mp; i += (int64_t)gridDim.x * EW) {
+    const int r = (int)(i / Mp), c = (int)(i % Mp);
+    if (r < M && c < M) {
+      Z x = c_neg(es[(int64_t)r * M + c]);
+      if (r == c) x = c_add(x, Z{dd{Ez, 0.0}, dd{eta, 0.0}});
+      A[(int64_t)r * M + c] = x;
+      X64[i] = D{to_d(x.re), to_d(x.im)};
     } else {
-      a[i] = Vdrc;
-      b[i] = Vrc;
-      Vf[i] = Vdrc;
-      Vb[i] = Vrc;
+      X64[i] = D{r == c ? 1.0 : 0.0, 0.0};
     }
   }
-  scale = wg_max(scale, sv);
-  __syncthreads();
+}
 
-  int flags = 0, it = 0;
-  bool converged = false;
-  for (it = 1; it <= max_iter; ++it) {
-    for (int64_t i = tid; i < MM; i += nt) {
-      const int r = (int)(i / M), c = (int)(i % M);
-      C x = c_neg(eps[i]);
-      if (r == c) x = c_add(x, z);
-      X[i] = x;
-    }
-    __syncthreads();
-    flags |= wg_gauss_jordan<dd>(X, M, M, M, q, colj, prow, sv, si);
-    wg_invert_perm(q, pinv, M);
-    // g = X[:, pinv] -> store in t1 (free at this point)
-    for (int64_t i = tid; i < MM; i += nt) {
-      const int r = (int)(i / M), c = (int)(i % M);
-      t1[i] = X[(int64_t)r * M + pinv[c]];
-    }
-    __syncthreads();
-    wg_gemm<dd>(ga, M, t1, M, a, M, M, M, M, false, gemm_lds);   // g a
-    wg_gemm<dd>(gb, M, t1, M, b, M, M, M, M, false, gemm_lds);   // g b
-    wg_gemm<dd>(t1, M, a, M, gb, M, M, M, M, false, gemm_lds);   // a g b
-    wg_gemm<dd>(t2, M, b, M, ga, M, M, M, M, false, gemm_lds);   // b g a
-    wg_gemm<dd>(a2, M, a, M, ga, M, M, M, M, false, gemm_lds);   // a g a
-    wg_gemm<dd>(b2, M, b, M, gb, M, M, M, M, false, gemm_lds);   // b g b
-    double amax = 0.0;
-    for (int64_t i = tid; i < MM; i += nt) {
-      eps_s[i] = c_add(eps_s[i], t1[i]);
-      eps[i] = c_add(eps[i], c_add(t1[i], t2[i]));
-      a[i] = a2[i];
-      b[i] = b2[i];
-      amax = fmax(amax, fmax(c_abs1(a2[i]), c_abs1(b2[i])));
-    }
-    amax = wg_max(amax, sv);
-    __syncthreads();
-    if (!(amax == amax) || isinf(amax)) {
-      flags |= KNIT_P_NONFINITE;
-      break;
-    }
-    if (amax < tol * scale) {
-      converged = true;
-      break;
-    }
+// eps_s += t1, [eps_r += t2], eps += t1 + t2; max |a_new|, |b_new| -> amax.
+__global__ void __launch_bounds__(EW) dec_update_kernel(int M, char *ws, Slab sl, int an, int bn, int both,
+                                                        DecState *st) {
+  __shared__ double red[EW / 64];
+  const int e = blockIdx.y;
+  if (st[e].done) return;
+  Z *eps_s = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_S]));
+  Z *eps_r = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_R]));
+  Z *eps = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS]));
+  const Z *t1 = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[ZT1]));
+  const Z *t2 = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[ZT2]));
+  const Z *a = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[an]));
+  const Z *b = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[bn]));
+  double amax = 0.0;
+  bool nan = false;
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW) {
+    eps_s[i] = c_add(eps_s[i], t1[i]);
+    if (both) eps_r[i] = c_add(eps_r[i], t2[i]);
+    eps[i] = c_add(eps[i], c_add(t1[i], t2[i]));
+    const double m = fmax(fabs(a[i].re.hi) + fabs(a[i].im.hi), fabs(b[i].re.hi) + fabs(b[i].im.hi));
+    if (m != m) nan = true;
+    else amax = fmax(amax, m);
   }
-  if (!converged) flags |= KNIT_P_NOCONV;
+  if (nan) amax = __builtin_inf();
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < EW / 64; ++w) amax = fmax(amax, red[w]);
+    amax = fmax(amax, red[0]);
+    atomicMax(&st[e].amax, (unsigned long long)__double_as_longlong(amax));
+  }
+}
 
-  // g = (z - eps_s)^{-1};  Sigma = Vf g Vb
-  for (int64_t i = tid; i < MM; i += nt) {
-    const int r = (int)(i / M), c = (int)(i % M);
-    C x = c_neg(eps_s[i]);
-    if (r == c) x = c_add(x, z);
-    X[i] = x;
+// One thread per energy: count the step, decide convergence.
+__global__ void dec_decide_kernel(DecState *st, int nE, double tol, int max_iter) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nE || st[e].done) return;
+  const double amax = __longlong_as_double((long long)st[e].amax);
+  const double scale = __longlong_as_double((long long)st[e].scale);
+  st[e].amax = 0ull;
+  const int it = ++st[e].iters;
+  if (st[e].flags & KNIT_P_SINGULAR) {
+    st[e].done = 1;
+  } else if (!isfinite(amax)) {
+    st[e].flags |= KNIT_P_NONFINITE;
+    st[e].done = 1;
+  } else if (amax < tol * scale) {
+    st[e].done = 1;
+  } else if (it >= max_iter) {
+    st[e].flags |= KNIT_P_NOCONV;
+    st[e].done = 1;
   }
-  __syncthreads();
-  flags |= wg_gauss_jordan<dd>(X, M, M, M, q, colj, prow, sv, si);
-  wg_invert_perm(q, pinv, M);
-  for (int64_t i = tid; i < MM; i += nt) {
-    const int r = (int)(i / M), c = (int)(i % M);
-    t1[i] = X[(int64_t)r * M + pinv[c]];
-  }
-  __syncthreads();
-  wg_gemm<dd>(t2, M, Vf, M, t1, M, M, M, M, false, gemm_lds);
-  wg_gemm<dd>(ga, M, t2, M, Vb, M, M, M, M, false, gemm_lds);
+}
+
+// sigma (FP64) from the dd product; NaN for failed energies; status words.
+__global__ void __launch_bounds__(EW) dec_store_kernel(int M, char *ws, Slab sl, int src, knit_z *sigma,
+                                                       int64_t sigma_stride, const DecState *st) {
+  const int e = blockIdx.y;
+  const Z *s = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[src]));
+  knit_z *out = sigma + (int64_t)e * sigma_stride;
+  const bool bad = (st[e].flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) != 0;
   const double qnan = __builtin_nan("");
-  knit_z *out = sigma + (int64_t)e * MM;
-  bool bad = (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) != 0;
-  for (int64_t i = tid; i < MM; i += nt) {
-    cpx<double> v = {r_to_double(ga[i].re), r_to_double(ga[i].im)};
-    if (bad) v = {qnan, qnan};
-    st_z(out + i, v);
-  }
-  if (tid == 0) {
-    pstatus[e] = flags;
-    if (iters) iters[e] = it > max_iter ? max_iter : it;
-  }
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW)
+    st_z(out + i, bad ? D{qnan, qnan} : D{to_d(s[i].re), to_d(s[i].im)});
+}
+
+__global__ void dec_status_kernel(const DecState *st, int nE, int max_iter, int32_t *pstatus, int32_t *iters) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nE) return;
+  pstatus[e] = st[e].flags;
+  if (iters) iters[e] = st[e].iters < max_iter ? st[e].iters : max_iter;
+}
+
+#pragma clang fp contract(fast)
+
+// Host-side launch helpers.
+struct Ctx {
+  StripDev s;
+  int M, Mp, nE;
+  Slab sl;
+  char *ws;
+  DecState *st;
+  hipStream_t stream;
+  Z *zb(int i) const { return reinterpret_cast<Z *>(ws + sl.z[i]); }
+};
+
+hipError_t gemm_zz(const Ctx &c, int a, int b, int out, double cI = 0.0, int neg = 0, int check = 1) {
+  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
+  hipLaunchKernelGGL((dd_gemm_kernel<Z, Z>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), c.zb(b),
+                     (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
+  return hipGetLastError();
+}
+
+// products with the FP64 inverse X0 as the left (dz) or right (zd) factor
+hipError_t gemm_dz(const Ctx &c, int b, int out, double cI, int neg, int check) {
+  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
+  const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
+  hipLaunchKernelGGL((dd_gemm_kernel<D, Z>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, X, c.zb(b),
+                     (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
+  return hipGetLastError();
+}
+hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) {
+  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
+  const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
+  hipLaunchKernelGGL((dd_gemm_kernel<Z, D>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), X,
+                     (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
+  return hipGetLastError();
+}
+
+// g = (z - es)^{-1} into ZXB: FP64 matrix-core inverse X0, then two Newton
+// steps X <- X (2I - A X) in double-double.
+hipError_t inverse_dd(const Ctx &c, const double *E, double eta, int src, int check) {
+  hipError_t err;
+  hipLaunchKernelGGL(dec_form_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.M, c.Mp, E, eta, c.ws, c.sl,
+                     src, c.st, check);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  const int64_t dstride = (int64_t)(c.sl.bytes / sizeof(D));
+  const int sst = (int)(sizeof(DecState) / sizeof(int32_t));
+  err = launch_inverse_fp64(reinterpret_cast<D *>(c.ws + c.sl.x64), dstride,
+                            reinterpret_cast<D *>(c.ws + c.sl.scr), dstride, c.M,
+                            reinterpret_cast<D *>(c.ws + c.sl.xi64), dstride, check ? &c.st->done : nullptr, sst,
+                            &c.st->flags, sst, c.nE, c.stream);
+  if (err != hipSuccess) return err;
+  if ((err = gemm_zd(c, ZA, ZR, 2.0, 1, check)) != hipSuccess) return err;   // R  = 2I - A X0
+  if ((err = gemm_dz(c, ZR, ZXA, 0.0, 0, check)) != hipSuccess) return err;  // XA = X0 R
+  if ((err = gemm_zz(c, ZA, ZXA, ZR, 2.0, 1, check)) != hipSuccess) return err;   // R  = 2I - A XA
+  return gemm_zz(c, ZXA, ZR, ZXB, 0.0, 0, check);                                // XB = XA R
 }
 
 }  // namespace
 
-size_t decimation_bytes_per_energy(int M) {
-  size_t b = (size_t)NBUF * M * M * sizeof(cpx<dd>);
-  return (b + 255) & ~size_t(255);
+size_t decimation_workspace(int M, int nE) {
+  const size_t head = (((size_t)nE * sizeof(DecState)) + 255) & ~size_t(255);
+  return head + (size_t)nE * slab_of(M).bytes;
 }
 
-static size_t decimation_lds_bytes(int M) {
-  size_t b = 2 * (size_t)M * sizeof(int) + 8 + (WG / WAVE) * (sizeof(double) + sizeof(int)) + 32 + 16;
-  size_t gj = 2 * (size_t)M * sizeof(cpx<dd>);
-  size_t gm = 2 * 32 * 16 * sizeof(cpx<dd>);
-  return b + (gj > gm ? gj : gm);
-}
-
-hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta,
-                             double tol, int max_iter, knit_z *sigma, int32_t *iters,
-                             int32_t *pstatus, void *ws, size_t per_energy_bytes,
+hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta, double tol,
+                             int max_iter, knit_z *sigma, int32_t *iters, int32_t *pstatus, void *ws,
                              hipStream_t stream) {
-  size_t lds = decimation_lds_bytes(s.M);
-  if (lds > 65536) {
-    hipError_t err = hipFuncSetAttribute((const void *)decimation_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err != hipSuccess) return err;
+  if (nE <= 0) return hipSuccess;
+  if (mfma_padded(s.M) > 512) return hipErrorInvalidValue;
+  Ctx c;
+  c.s = s;
+  c.M = s.M;
+  c.Mp = mfma_padded(s.M);
+  c.nE = nE;
+  c.sl = slab_of(s.M);
+  c.st = reinterpret_cast<DecState *>(ws);
+  c.ws = reinterpret_cast<char *>(ws) + ((((size_t)nE * sizeof(DecState)) + 255) & ~size_t(255));
+  c.stream = stream;
+  const int both = side == 2;
+  hipError_t err;
+  hipLaunchKernelGGL(dec_reset_state_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE);
+  hipLaunchKernelGGL(dec_init_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, s, side, c.ws, c.sl, c.st);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  for (int it = 0; it < max_iter; ++it) {
+    const int a = (it & 1) ? ZA1 : ZA0, b = (it & 1) ? ZB1 : ZB0;
+    const int an = (it & 1) ? ZA0 : ZA1, bn = (it & 1) ? ZB0 : ZB1;
+    if ((err = inverse_dd(c, E, eta, ZEPS, 1)) != hipSuccess) return err;   // g_k in ZXB
+    if ((err = gemm_zz(c, ZXB, a, ZGA)) != hipSuccess) return err;          // g a
+    if ((err = gemm_zz(c, ZXB, b, ZGB)) != hipSuccess) return err;          // g b
+    if ((err = gemm_zz(c, a, ZGB, ZT1)) != hipSuccess) return err;          // a g b
+    if ((err = gemm_zz(c, b, ZGA, ZT2)) != hipSuccess) return err;          // b g a
+    if ((err = gemm_zz(c, a, ZGA, an)) != hipSuccess) return err;           // a g a
+    if ((err = gemm_zz(c, b, ZGB, bn)) != hipSuccess) return err;           // b g b
+    hipLaunchKernelGGL(dec_update_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, c.M, c.ws, c.sl, an, bn, both,
+                       c.st);
+    hipLaunchKernelGGL(dec_decide_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE, tol, max_iter);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  hipLaunchKernelGGL(decimation_kernel, dim3(nE), dim3(WG), lds, stream, s, side, E, nE, eta, tol,
-                     max_iter, sigma, iters, pstatus, reinterpret_cast<char *>(ws), per_energy_bytes);
+  // surface Green functions and self-energies:
+  //   left (or the one requested): Sigma = Vf g Vb with g = (z - eps_s)^{-1}
+  //   side 2, right:               Sigma = Vb g Vf with g = (z - eps_r)^{-1}
+  for (int surf = 0; surf < (both ? 2 : 1); ++surf) {
+    if ((err = inverse_dd(c, E, eta, surf == 0 ? ZEPS_S : ZEPS_R, 0)) != hipSuccess) return err;
+    if ((err = gemm_zz(c, surf == 0 ? ZVF : ZVB, ZXB, ZT1, 0.0, 0, 0)) != hipSuccess) return err;
+    if ((err = gemm_zz(c, ZT1, surf == 0 ? ZVB : ZVF, ZT2, 0.0, 0, 0)) != hipSuccess) return err;
+    hipLaunchKernelGGL(dec_store_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, c.M, c.ws, c.sl, (int)ZT2,
+                       sigma + (int64_t)surf * nE * c.M * c.M, (int64_t)c.M * c.M, c.st);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(dec_status_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE, max_iter, pstatus,
+                     iters);
   return hipGetLastError();
 }
 

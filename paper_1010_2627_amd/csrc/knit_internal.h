@@ -38,9 +38,16 @@ __device__ __forceinline__ cpx<double> strip_V(const StripDev &s, int a, int b) 
 // Launch wrappers (defined in the .hip files).
 hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta,
                              double tol, int max_iter, knit_z *sigma, int32_t *iters,
-                             int32_t *pstatus, void *ws, size_t per_energy_bytes,
-                             hipStream_t stream);
-size_t decimation_bytes_per_energy(int M);
+                             int32_t *pstatus, void *ws, hipStream_t stream);
+size_t decimation_workspace(int M, int nE);
+
+// Matrix-core FP64 inverses of n identity-padded [Mp][Mp] matrices (Mp = the
+// slice padding of M, at most 512), in place; natural-order inverses to out.
+int mfma_padded(int M);
+size_t inverse_fp64_scratch_elems(int M);
+hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64_t sstride, int M,
+                               cpx<double> *out, int64_t ostride, const int32_t *skip, int skip_stride,
+                               int32_t *flags, int flags_stride, int n, hipStream_t stream);
 
 constexpr int SWEEP_MAX_GRID = 512;   // upper bound of resident sweep workgroups
 

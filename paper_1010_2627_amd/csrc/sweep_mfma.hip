@@ -607,6 +607,38 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
   }
 }
 
+// Batched FP64 inverse on the matrix cores, one workgroup per matrix: X_e
+// ([Mp][Mp], padded with an identity block) is reduced in place by the
+// two-level elimination and its inverse, in natural order, goes to out_e
+// ([M][M]).  Matrices whose skip flag is set are left alone; a singular pivot
+// sets KNIT_P_SINGULAR in flags[e].
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+inverse_fp64_kernel(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64_t sstride, int M, int Mp,
+                    cpx<double> *out, int64_t ostride, const int32_t *skip, int skip_stride, int32_t *flags,
+                    int flags_stride) {
+  __shared__ int q[NT];
+  __shared__ int pinv[NT];
+  __shared__ double sv[32];
+  __shared__ int si[64];
+  __shared__ cpx<double> xchg[2 * 32];
+  __shared__ cpx<double> prow[32];
+  const int e = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  if (skip && skip[(int64_t)e * skip_stride]) return;
+  cpx<double> *Xe = X + (int64_t)e * xstride;
+  cpx<double> *Sb = scratch + (int64_t)e * sstride;
+  cpx<double> *Sd = Sb + (int64_t)2 * Mp * 64;
+  const int fl = gj_two_level<double, NT>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
+  for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
+  __syncthreads();
+  cpx<double> *o = out + (int64_t)e * ostride;
+  for (int64_t i = tid; i < (int64_t)M * M; i += nt) {
+    const int a = (int)(i / M), b = (int)(i % M);
+    o[i] = Xe[(int64_t)q[a] * Mp + pinv[b]];
+  }
+  if (fl && tid == 0) atomicOr(flags + (int64_t)e * flags_stride, fl);
+}
+
 }  // namespace
 
 int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
@@ -624,6 +656,26 @@ size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
 }
 
 bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= 512; }
+
+size_t inverse_fp64_scratch_elems(int M) {
+  const size_t Mp = (size_t)mfma_padded(M);
+  return 2 * Mp * 64 + 64 * Mp;
+}
+
+hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64_t sstride, int M,
+                               cpx<double> *out, int64_t ostride, const int32_t *skip, int skip_stride,
+                               int32_t *flags, int flags_stride, int n, hipStream_t stream) {
+  const int Mp = mfma_padded(M);
+  if (Mp > 512) return hipErrorInvalidValue;
+  if (n <= 0) return hipSuccess;
+  if (Mp <= 256)
+    hipLaunchKernelGGL(inverse_fp64_kernel<256>, dim3(n), dim3(256), 0, stream, X, xstride, scratch, sstride, M,
+                       Mp, out, ostride, skip, skip_stride, flags, flags_stride);
+  else
+    hipLaunchKernelGGL(inverse_fp64_kernel<512>, dim3(n), dim3(512), 0, stream, X, xstride, scratch, sstride, M,
+                       Mp, out, ostride, skip, skip_stride, flags, flags_stride);
+  return hipGetLastError();
+}
 
 // Workspace: a 256-byte header (queue counter) then one slab per workgroup.
 size_t sweep_mfma_workspace(int Mmax, int precision, int P) {

@@ -159,14 +159,17 @@ class ProblemTable:
 
 def knit_lead_selfenergy(strip: DeviceStrip, side: int, E: torch.Tensor, eta: float = 1e-13,
                          tol: float = 1e-16, max_iter: int = 100, stream=None):
-    """Sigma of the left (side 0) or right (side 1) lead at energies E (device float64 [nE]).
+    """Sigma of the left (side 0) or right (side 1) lead, or of both (side 2), at energies E
+    (device float64 [nE]).
 
-    Returns (sigma [nE, M, M] complex128, iters [nE] int32, status [nE] int32), all on the device.
+    Returns (sigma, iters [nE] int32, status [nE] int32), all on the device; sigma is
+    [nE, M, M] complex128, or [2, nE, M, M] (left, right) for side 2.
     """
     assert E.dtype == torch.float64 and E.is_cuda and E.is_contiguous()
     nE = E.numel()
     dev = E.device
-    sigma = torch.empty((nE, strip.M, strip.M), dtype=torch.complex128, device=dev)
+    shape = (2, nE, strip.M, strip.M) if side == 2 else (nE, strip.M, strip.M)
+    sigma = torch.empty(shape, dtype=torch.complex128, device=dev)
     iters = torch.zeros(nE, dtype=torch.int32, device=dev)
     status = torch.zeros(nE, dtype=torch.int32, device=dev)
     cs = strip.c()

@@ -92,11 +92,11 @@ class Batch:
                 continue
             Et = torch.as_tensor(np.asarray(E, dtype=np.float64), device=self.device)
             base, n = self.sigma_base[si], len(E) * ds.M * ds.M
-            for side, dst in ((0, self.sigmaL), (1, self.sigmaR)):
-                sig, it, st = K.knit_lead_selfenergy(ds, side, Et, eta, tol, max_iter, stream)
-                dst[base:base + n].copy_(sig.reshape(-1))
-                stats.append(st)
-                its.append(it)
+            sig, it, st = K.knit_lead_selfenergy(ds, 2, Et, eta, tol, max_iter, stream)
+            self.sigmaL[base:base + n].copy_(sig[0].reshape(-1))
+            self.sigmaR[base:base + n].copy_(sig[1].reshape(-1))
+            stats.append(st)
+            its.append(it)
         self.sigma_status = torch.cat(stats) if stats else None
         self.sigma_iters = torch.cat(its) if its else None
         return self.sigmaL, self.sigmaR

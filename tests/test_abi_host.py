@@ -126,7 +126,8 @@ def test_selfenergy_argument_checks(K):
         a = args(**kw)
         return f(ctypes.byref(s), a["side"], a["E"], a["nE"], a["eta"], a["tol"], a["it"], a["sig"],
                  a["iters"], a["st"], a["ws"], a["wsb"], None)
-    assert call(side=2) == K.KNIT_E_ARG
+    assert call(side=3) == K.KNIT_E_ARG
+    assert call(side=-1) == K.KNIT_E_ARG
     assert call(eta=0.0) == K.KNIT_E_ARG
     assert call(eta=float("inf")) == K.KNIT_E_ARG
     assert call(tol=-1.0) == K.KNIT_E_ARG
@@ -136,6 +137,9 @@ def test_selfenergy_argument_checks(K):
     assert call(E=None) == K.KNIT_E_ARG
     assert call(wsb=ws_need - 1) == K.KNIT_E_WORKSPACE
     assert call(nE=0) == K.KNIT_OK
+    big = _strip(M=520)
+    assert f(ctypes.byref(big), 0, E, 3, 1e-13, 1e-16, 50, FAKE, None, FAKE, FAKE, 1 << 40, None) \
+        == K.KNIT_E_UNSUPPORTED
     bad = _strip(M=6, norb=4)
     assert f(ctypes.byref(bad), 0, E, 3, 1e-13, 1e-16, 50, FAKE, None, FAKE, FAKE, 1 << 40, None) == K.KNIT_E_ARG
 

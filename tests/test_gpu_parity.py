@@ -63,7 +63,12 @@ def test_selfenergy_matches_oracle_modes(case):
     Et = torch.as_tensor(E, device="cuda")
     sLg, itL, stL = knit.knit_lead_selfenergy(ds, 0, Et)
     sRg, itR, stR = knit.knit_lead_selfenergy(ds, 1, Et)
+    sBg, itB, stB = knit.knit_lead_selfenergy(ds, 2, Et)
     torch.cuda.synchronize()
+    # both leads from one doubling run: the same arithmetic, so the same bits
+    assert int(stB.abs().sum()) == 0
+    assert torch.equal(sBg[0], sLg) and torch.equal(sBg[1], sRg)
+    assert torch.equal(itB, itL)
     sL, sR = _oracle_sigmas(st, E)
     assert int(stL.abs().sum()) == 0 and int(stR.abs().sum()) == 0
     # decimation runs at z = E + i*1e-13: its bias is ~eta / (group velocity), which the
