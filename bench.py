@@ -36,6 +36,21 @@ METRIC = "RGF slice-steps/s at W=256, FP32-MFMA+refine vs FP64; T(E) points/s at
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32_refine": 157.3}
 TOL_PER_CHANNEL = 1e-6
 
+# HBM bytes per launch of the FP64 sweep kernel from the calibrated FETCH_SIZE /
+# WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
+# prefix is given; any other source reports null.
+MEASURED_TRAFFIC = {
+    "c4": {"sha": "818c5b04ff44b4f1", "bytes": 9.737e13,
+           "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
+}
+
+
+def sweep_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1010_2627_amd", "csrc", "sweep_mfma.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 WORKLOADS = {
     # name: builder kwargs and description
     "c4": dict(kind="rashba", W=256, L=512, w=2.0, n_energies=64, n_seeds=8,
@@ -215,6 +230,8 @@ def main():
     nopen = np.tile(open_channels(cfg, b), len(b.realizations))
 
     achieved = flops_per_pass / tw64 / 1e12
+    tr = MEASURED_TRAFFIC.get(args.workload)
+    traffic = tr["bytes"] if tr and tr["sha"] == sweep_source_sha() else None
     out = {
         "metric": METRIC,
         "value": steps_per_pass / wall64,
@@ -237,7 +254,9 @@ def main():
         "t_points_per_s": b.P / wall64,
         "problems_with_status": bad64,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (calibrated counters)",
+                     "traffic_source": tr["profile"] if traffic else None,
                      "kernel": "sweep_mfma_kernel<double> (FP64 MFMA)",
                      "flops_per_slice_step": "16*M^3 (8M^3 inverse + 8M^3 propagator)"},
     }
