@@ -48,6 +48,7 @@ extern "C" {
 #define KNIT_MAX_M 1024        /* largest slice dimension */
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
 #define KNIT_MAX_SELFENERGY_M 512   /* largest slice for knit_lead_selfenergy */
+#define KNIT_TUNING_CLASSES 16      /* padded slice classes 32, 64, .., 512 */
 
 typedef struct knit_z { double re, im; } knit_z;
 
@@ -156,6 +157,32 @@ size_t knit_lead_selfenergy_workspace(const knit_strip *strip, int32_t nE);
 int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E, int32_t nE,
                          double eta, double tol, int32_t max_iter, knit_z *sigma, int32_t *iters,
                          int32_t *pstatus, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Launch tuning of the matrix-core sweep (batching: workgroup shape, occupancy
+ * and queue order), one entry per precision and padded-slice class
+ * cls = Mp / 32 - 1 (Mp = slice dimension rounded up to 32, the largest of
+ * the batch).  The library's defaults apply to classes never set; an entry
+ * that does not fit the class (threads < Mp) is ignored at launch.
+ *
+ *   threads    256 or 512 threads per workgroup (one panel row per thread,
+ *              so threads >= Mp)
+ *   wg_per_cu  resident workgroups per compute unit the grid is sized for (1, 2)
+ *   order      0: problems in table order; 1: longest (Mp^3 L) first
+ *
+ * Process-wide; set before the sweeps that should use it (calls that run
+ * concurrently with a change see either the old or the new entry).
+ * knit_sweep_tuning_set with t == NULL restores the default.  Both return
+ * KNIT_E_ARG for a bad precision, class or entry.
+ */
+typedef struct knit_sweep_tuning {
+  int32_t threads;
+  int32_t wg_per_cu;
+  int32_t order;
+} knit_sweep_tuning;
+
+int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tuning *t);
+int knit_sweep_tuning_get(int32_t precision, int32_t cls, knit_sweep_tuning *t);
 
 /*
  * Left-to-right slice recursion (section 1, basic RGF) for a batch of P

@@ -145,6 +145,19 @@ int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_proble
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 
+int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tuning *t) {
+  if (!precision_ok(precision) || cls < 0 || cls >= KNIT_TUNING_CLASSES) return KNIT_E_ARG;
+  if (t && !sweep_tuning_valid(32 * (cls + 1), *t)) return KNIT_E_ARG;
+  sweep_tuning_set(precision, cls, t);
+  return KNIT_OK;
+}
+
+int knit_sweep_tuning_get(int32_t precision, int32_t cls, knit_sweep_tuning *t) {
+  if (!precision_ok(precision) || cls < 0 || cls >= KNIT_TUNING_CLASSES || !t) return KNIT_E_ARG;
+  *t = sweep_tuning_get(precision, 32 * (cls + 1));
+  return KNIT_OK;
+}
+
 int knit_transmission(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
                       const knit_problem *probs_dev, int32_t P, const knit_z *sigmaL,
                       const knit_z *sigmaR, const knit_z *G1N, const knit_z *GN1,

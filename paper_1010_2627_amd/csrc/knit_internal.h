@@ -52,6 +52,10 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
 constexpr int SWEEP_MAX_GRID = 512;   // upper bound of resident sweep workgroups
 
 bool sweep_mfma_supports(int Mmax);
+int sweep_tuning_set(int precision, int cls, const knit_sweep_tuning *t);
+knit_sweep_tuning sweep_tuning_get(int precision, int Mpmax);
+knit_sweep_tuning sweep_default_tuning(int Mpmax);
+bool sweep_tuning_valid(int Mpmax, const knit_sweep_tuning &t);
 size_t sweep_mfma_workspace(int Mmax, int precision, int P);
 hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
                              const knit_z *sigmaL, const knit_z *sigmaR, int precision, knit_z *G1N,

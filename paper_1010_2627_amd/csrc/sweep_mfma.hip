@@ -26,6 +26,8 @@
 //                the product in FP64, then [g_n; G_1n] = [X0; G0] (I + R) with
 //                the correction product in FP32.
 
+#include <mutex>
+
 #include "knit_internal.h"
 #include "knit_mfma.h"
 #include "knit_slice.h"
@@ -447,14 +449,51 @@ __device__ void gather_vg(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int 
   }
 }
 
-__global__ void reset_queue_kernel(unsigned int *counter) { *counter = 0u; }
+
+// Queue order for the persistent sweep.  policy 0: problem order.  policy 1:
+// longest processing time first, on the cost Mp^3 L binned at four bins per
+// octave (a counting sort, one workgroup; order within a bin is whatever the
+// atomics give, which does not change any result).  Also clears the queue.
+constexpr int LPT_BINS = 256;
+__global__ void __launch_bounds__(1024) order_kernel(StripTable tab, const knit_problem *probs, int P, int policy,
+                                                     int *order, unsigned int *queue) {
+  __shared__ unsigned int cnt[LPT_BINS];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) *queue = 0u;
+  if (policy == 0) {
+    for (int p = tid; p < P; p += nt) order[p] = p;
+    return;
+  }
+  auto bin_of = [&](int p) {
+    const knit_problem pr = probs[p];
+    const double Mp = (double)((tab.s[pr.strip].M + MPAD - 1) / MPAD * MPAD);
+    const double cost = Mp * Mp * Mp * (double)(pr.L > 0 ? pr.L : 1);
+    int b = (int)(4.0 * log2(cost));
+    return b < 0 ? 0 : (b >= LPT_BINS ? LPT_BINS - 1 : b);
+  };
+  for (int b = tid; b < LPT_BINS; b += nt) cnt[b] = 0u;
+  __syncthreads();
+  for (int p = tid; p < P; p += nt) atomicAdd(&cnt[bin_of(p)], 1u);
+  __syncthreads();
+  if (tid == 0) {   // start of each bin, costliest bin first
+    unsigned int run = 0;
+    for (int b = LPT_BINS - 1; b >= 0; --b) {
+      const unsigned int c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int p = tid; p < P; p += nt) order[atomicAdd(&cnt[bin_of(p)], 1u)] = p;
+}
 
 template <class RG, class RS, bool REFINE, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sweep_mfma_kernel(StripTable tab, const knit_problem *probs, int P,
                                                         const knit_z *onsite, const knit_z *sigmaL,
                                                         const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
                                                         knit_z *GNN, int32_t *pstatus, char *ws,
-                                                        size_t slab_bytes, int Mpmax, unsigned int *queue) {
+                                                        size_t slab_bytes, int Mpmax, unsigned int *queue,
+                                                        const int *order) {
   __shared__ int next_p;
   __shared__ int qa[NT], qb[NT];        // row order of the current / previous elimination
   __shared__ int pa[NT], pb[NT];        // and its inverse (column order of the inverse)
@@ -485,9 +524,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
   for (;;) {
     if (tid == 0) next_p = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    const int p = next_p;
+    const int pi = next_p;
     __syncthreads();
-    if (p >= P) break;
+    if (pi >= P) break;
+    const int p = order[pi];
     const knit_problem pr = probs[p];
     const StripDev s = tab.s[pr.strip];
     const int M = s.M, no = s.norb, L = pr.L;
@@ -677,10 +717,56 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
   return hipGetLastError();
 }
 
-// Workspace: a 256-byte header (queue counter) then one slab per workgroup.
+// Workspace: a 256-byte header (queue counter), the queue order [P] (padded to
+// 256 bytes), then one slab per workgroup.
+static size_t order_bytes(int P) { return (((size_t)P * sizeof(int)) + 255) & ~size_t(255); }
+
 size_t sweep_mfma_workspace(int Mmax, int precision, int P) {
   const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
-  return 256 + sweep_mfma_slab_bytes(Mmax, precision) * (size_t)grid;
+  return 256 + order_bytes(P) + sweep_mfma_slab_bytes(Mmax, precision) * (size_t)grid;
+}
+
+// Launch tuning per (precision, padded-slice class), set by the autotuner.
+namespace {
+std::mutex tuning_mu;
+knit_sweep_tuning tuning_table[3][KNIT_TUNING_CLASSES];
+bool tuning_set_flag[3][KNIT_TUNING_CLASSES];
+}  // namespace
+
+knit_sweep_tuning sweep_default_tuning(int Mpmax) {
+  knit_sweep_tuning t;
+  t.threads = Mpmax <= 256 ? 256 : 512;
+  t.wg_per_cu = Mpmax <= 256 ? 2 : 1;
+  t.order = 1;
+  return t;
+}
+
+bool sweep_tuning_valid(int Mpmax, const knit_sweep_tuning &t) {
+  if (t.threads != 256 && t.threads != 512) return false;
+  if (t.threads < Mpmax) return false;                 // one panel row per thread
+  if (t.wg_per_cu < 1 || t.wg_per_cu > 2) return false;
+  if (t.order != 0 && t.order != 1) return false;
+  return true;
+}
+
+int sweep_tuning_set(int precision, int cls, const knit_sweep_tuning *t) {
+  std::lock_guard<std::mutex> lk(tuning_mu);
+  if (t) {
+    tuning_table[precision][cls] = *t;
+    tuning_set_flag[precision][cls] = true;
+  } else {
+    tuning_set_flag[precision][cls] = false;
+  }
+  return 0;
+}
+
+knit_sweep_tuning sweep_tuning_get(int precision, int Mpmax) {
+  const int cls = Mpmax / 32 - 1;
+  std::lock_guard<std::mutex> lk(tuning_mu);
+  if (cls >= 0 && cls < KNIT_TUNING_CLASSES && tuning_set_flag[precision][cls] &&
+      sweep_tuning_valid(Mpmax, tuning_table[precision][cls]))
+    return tuning_table[precision][cls];
+  return sweep_default_tuning(Mpmax);
 }
 
 hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
@@ -688,24 +774,27 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
                              knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, int Mmax,
                              hipStream_t stream) {
   unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
-  char *w = reinterpret_cast<char *>(ws) + 256;
+  int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
+  char *w = reinterpret_cast<char *>(ws) + 256 + order_bytes(P);
   const size_t slab = sweep_mfma_slab_bytes(Mmax, precision);
   const int Mpmax = mfma_padded(Mmax);
-  // workgroup of 256 threads (two resident per compute unit) when the padded
-  // slice fits one panel row per thread, else 512
-  const bool small = Mpmax <= 256;
+  // workgroup size, workgroups per compute unit and queue order from the
+  // tuning table (default: 256 threads, two per compute unit, when the padded
+  // slice fits one panel row per thread, else 512 threads, one per unit; LPT)
+  const knit_sweep_tuning tune = sweep_tuning_get(precision, Mpmax);
+  const bool small = tune.threads == 256;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  int grid = small ? 2 * ncu : ncu;
+  int grid = tune.wg_per_cu * ncu;
   if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
   if (grid > P) grid = P;
-  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(1), 0, stream, queue);
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
 #define KNIT_LAUNCH(RG, RS, RF, NT)                                                                          \
   hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, \
-                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue)
+                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order)
   if (precision == KNIT_FP64) {
     if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
   } else if (precision == KNIT_FP32) {

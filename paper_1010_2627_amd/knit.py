@@ -64,9 +64,22 @@ _lib.knit_ldos.restype = c_i32
 _lib.knit_ldos.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp,
                            c_vp, c_sz, c_vp]
 
+
+
+class KnitSweepTuning(ctypes.Structure):
+    _fields_ = [("threads", c_i32), ("wg_per_cu", c_i32), ("order", c_i32)]
+
+
+KNIT_TUNING_CLASSES = 16
+_lib.knit_sweep_tuning_set.restype = c_i32
+_lib.knit_sweep_tuning_set.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTuning)]
+_lib.knit_sweep_tuning_get.restype = c_i32
+_lib.knit_sweep_tuning_get.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTuning)]
+
 EXPORTED = ["knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
-            "knit_transmission", "knit_ldos_workspace", "knit_ldos"]
+            "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
+            "knit_sweep_tuning_get"]
 
 
 class KnitError(RuntimeError):
@@ -81,6 +94,26 @@ def abi_version() -> int:
 
 def status_string(code: int) -> str:
     return _lib.knit_status_string(int(code)).decode()
+
+
+def tuning_class(Mp: int) -> int:
+    """Padded-slice class of the tuning table: Mp = 32 * ceil(M / 32), class Mp / 32 - 1."""
+    return (int(Mp) + 31) // 32 - 1
+
+
+def knit_sweep_tuning_set(precision, cls: int, threads: int | None = None, wg_per_cu: int = 1,
+                          order: int = 1):
+    """Set (or, with threads=None, reset to the default) one entry of the sweep tuning table."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    t = None if threads is None else ctypes.byref(KnitSweepTuning(int(threads), int(wg_per_cu), int(order)))
+    _check(_lib.knit_sweep_tuning_set(prec, int(cls), t), "knit_sweep_tuning_set")
+
+
+def knit_sweep_tuning_get(precision, cls: int) -> dict:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    t = KnitSweepTuning()
+    _check(_lib.knit_sweep_tuning_get(prec, int(cls), ctypes.byref(t)), "knit_sweep_tuning_get")
+    return {"threads": t.threads, "wg_per_cu": t.wg_per_cu, "order": t.order}
 
 
 def _ptr(t) -> int | None:

@@ -60,6 +60,10 @@ class Batch:
             self.sigma_base.append(spos)
             spos += len(E) * s.M * s.M
         self.sigma_elems = max(spos, 1)
+        # energies on the device (the self-energy call takes device energies; keeping them
+        # resident lets a whole step be captured in a graph)
+        self.denergies = [torch.as_tensor(np.asarray(E, dtype=np.float64), device=self.device)
+                          for E in self.energies]
         # problems: realization x energy of its strip class
         rows, meta = [], []
         out_pos = ldos_pos = 0
@@ -90,7 +94,7 @@ class Batch:
         for si, (ds, E) in enumerate(zip(self.dstrips, self.energies)):
             if len(E) == 0:
                 continue
-            Et = torch.as_tensor(np.asarray(E, dtype=np.float64), device=self.device)
+            Et = self.denergies[si]
             base, n = self.sigma_base[si], len(E) * ds.M * ds.M
             sig, it, st = K.knit_lead_selfenergy(ds, 2, Et, eta, tol, max_iter, stream)
             self.sigmaL[base:base + n].copy_(sig[0].reshape(-1))

@@ -1,0 +1,146 @@
+"""GPU batching: uneven batches in one persistent launch, queue order and launch
+shapes, graph capture of a whole step, and the autotuner.
+
+Parity is against the FP64 CPU oracle (its own lead self-energies and slice
+recursion); the other checks compare the library with itself bit for bit,
+because which workgroup computes a problem, and when, must not change any of
+its arithmetic.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")
+
+# small uneven batch: widths 8..64 (several padded classes, up to Mp = 64), lengths 3..40
+LAYOUT = dict(n_strips=10, wmin=8, wmax=64, wstep=8, lmin=3, lmax=40, dmin=0.5, dmax=3.0)
+
+
+def _uneven(n_energies=5):
+    from paper_1010_2627_amd import workload
+    return workload.uneven_batch(n_energies=n_energies, **LAYOUT)
+
+
+def _oracle_sigmas(b):
+    from oracle import leads as OL
+    sL, sR = [], []
+    for st, E in zip(b.strips, b.energies):
+        V = st.V_dense()
+        sL.append(np.stack([OL.sigma_modes(st.H0, V, e, "L") for e in E]))
+        sR.append(np.stack([OL.sigma_modes(st.H0, V, e, "R") for e in E]))
+    return sL, sR
+
+
+@gpu
+def test_uneven_batch_fp64_matches_oracle():
+    from oracle import rgf as OR
+    b = _uneven()
+    sL, sR = _oracle_sigmas(b)
+    b.set_sigmas(sL, sR)
+    G1N, _, _, status = b.sweep("fp64", gnn=False)
+    T = b.transmission(G1N)[0].cpu().numpy()
+    assert int(status.abs().sum()) == 0
+    for ri, r in enumerate(b.realizations):
+        st = b.strips[r.strip]
+        E = b.energies[r.strip]
+        res = OR.rgf_forward(st.H0, st.V_dense(), r.onsite, E, sL[r.strip], sR[r.strip])
+        Tref = OR.transmission_lr(sL[r.strip], sR[r.strip], res["G1N"])
+        for ei in range(len(E)):
+            p = ri * len(E) + ei
+            assert tuple(b.prob_meta[p]) == (ri, ei)
+            assert abs(T[p] - Tref[ei]) <= 1e-10 * max(1.0, abs(Tref[ei])), (ri, ei, T[p], Tref[ei])
+
+
+@gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_launch_shapes_and_queue_order_do_not_change_results(prec):
+    from paper_1010_2627_amd import autotune, knit as K
+    b = _uneven()
+    b.compute_sigmas()
+    Mp = (max(s.M for s in b.strips) + 31) // 32 * 32
+    cls = K.tuning_class(Mp)
+    ref = None
+    try:
+        for cand in autotune.candidates(Mp):
+            K.knit_sweep_tuning_set(prec, cls, **cand)
+            G1N, _, GNN, status = b.sweep(prec, gnn=True)
+            torch.cuda.synchronize()
+            assert int(status.abs().sum()) == 0
+            if ref is None:
+                ref = (G1N.clone(), GNN.clone())
+            else:
+                assert torch.equal(G1N, ref[0]), cand
+                assert torch.equal(GNN, ref[1]), cand
+    finally:
+        K.knit_sweep_tuning_set(prec, cls, None)
+
+
+@gpu
+def test_lpt_order_serves_costliest_first():
+    """The queue order the library writes into the workspace header: every problem once,
+    costs (Mp^3 L, binned) non-increasing."""
+    from paper_1010_2627_amd import knit as K
+    b = _uneven()
+    b.compute_sigmas()
+    ws = torch.zeros(K.knit_rgf_sweep_workspace(b.dstrips, b.probs, "fp64"), dtype=torch.uint8, device="cuda")
+    b.sweep("fp64", gnn=False, workspace=ws)
+    torch.cuda.synchronize()
+    order = ws[256:256 + 4 * b.P].view(torch.int32).cpu().numpy()
+    assert sorted(order.tolist()) == list(range(b.P))
+    Ms = np.array([b.strips[int(s)].M for s in b.probs.host["strip"]])
+    Mp = (Ms + 31) // 32 * 32
+    cost = (Mp.astype(np.float64) ** 3 * b.probs.host["L"])[order]
+    # binned at four bins per octave: a later problem is never costlier by more than one bin
+    assert np.all(cost[1:] <= cost[:-1] * 2 ** 0.25 * (1 + 1e-12))
+
+
+@gpu
+def test_graph_capture_of_a_whole_step_replays_bitwise():
+    """Self-energies, sweep and trace captured once, replayed three times with eager work
+    and host synchronisation in between; every replay equals the eager step bit for bit."""
+    b = _uneven(n_energies=3)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b.compute_sigmas()
+        G1N, _, _, _ = b.sweep("fp64", gnn=False)
+        T_eager = b.transmission(G1N)[0].clone()
+        sL_eager = b.sigmaL.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.compute_sigmas()
+        G1N_g, _, _, st_g = b.sweep("fp64", gnn=False)
+        T_g = b.transmission(G1N_g)[0]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        # unrelated eager work on the default stream between replays
+        x = torch.randn(1 << 20, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(T_g, T_eager), rep
+        assert torch.equal(b.sigmaL, sL_eager), rep
+        assert int(st_g.abs().sum()) == 0
+        del x
+
+
+@gpu
+def test_autotuner_installs_a_valid_entry(tmp_path):
+    from paper_1010_2627_amd import autotune, knit as K
+    b = _uneven()
+    b.compute_sigmas()
+    r = autotune.tune_batch(b, "fp64", sample_slices=4, repeats=1)
+    try:
+        assert r["best"] in autotune.candidates(r["Mp"])
+        assert K.knit_sweep_tuning_get("fp64", r["cls"]) == r["best"]
+        assert len(r["results"]) == len(autotune.candidates(r["Mp"]))
+        path = str(tmp_path / "t.json")
+        autotune.save(path, [r])
+        K.knit_sweep_tuning_set("fp64", r["cls"], None)
+        assert autotune.load(path) == 1
+        assert K.knit_sweep_tuning_get("fp64", r["cls"]) == r["best"]
+    finally:
+        K.knit_sweep_tuning_set("fp64", r["cls"], None)
