@@ -66,7 +66,11 @@ enum {
   KNIT_P_OK = 0,
   KNIT_P_SINGULAR = 1,      /* an exactly singular slice (zero pivot) */
   KNIT_P_NOCONV = 2,        /* decimation hit max_iter before convergence */
-  KNIT_P_NONFINITE = 4      /* NaN or Inf met in inputs or intermediates */
+  KNIT_P_NONFINITE = 4,     /* NaN or Inf met in inputs or intermediates */
+  KNIT_P_FALLBACK = 8       /* KNIT_FP32_REFINE only: a slice's FP32 inverse was too
+                               poor for one refinement step (largest residual entry above
+                               the refine threshold), so the problem was recomputed by
+                               the FP64 sweep in the same call; its outputs are FP64's */
 };
 
 /* Arithmetic of the slice sweep. */
@@ -185,6 +189,18 @@ int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tunin
 int knit_sweep_tuning_get(int32_t precision, int32_t cls, knit_sweep_tuning *t);
 
 /*
+ * Threshold of the KNIT_FP32_REFINE sweep (precision extension): after each
+ * slice's FP32 inverse X0, the FP64 residual R = I - A_n X0 is formed; one
+ * refinement step leaves a relative error of order |R|^2, so a problem whose
+ * largest residual entry exceeds the threshold (or is NaN) is marked
+ * KNIT_P_FALLBACK and recomputed in FP64.  Default 1e-3.  0 sends every
+ * problem to FP64; +Inf never does.  Process-wide; returns KNIT_E_ARG for a
+ * negative or NaN value.
+ */
+int knit_set_refine_threshold(double threshold);
+double knit_get_refine_threshold(void);
+
+/*
  * Left-to-right slice recursion (section 1, basic RGF) for a batch of P
  * problems, in one persistent launch.  Per problem:
  *   g_1 = (E - H_1 - Sigma_L - [L = 1] Sigma_R)^{-1}
@@ -200,7 +216,9 @@ int knit_sweep_tuning_get(int32_t precision, int32_t cls, knit_sweep_tuning *t);
  *   probs_dev          device [P] copy of the same table
  *   onsite             device on-site blocks addressed by onsite_off
  *   sigmaL, sigmaR     device self-energies addressed by sigma_off
- *   precision          KNIT_FP64, KNIT_FP32_REFINE or KNIT_FP32
+ *   precision          KNIT_FP64, KNIT_FP32_REFINE or KNIT_FP32 (with
+ *                      KNIT_FP32_REFINE, problems flagged KNIT_P_FALLBACK are
+ *                      recomputed in FP64 by a second launch of the same call)
  *   G1N                device output addressed by out_off (required)
  *   GN1, GNN           device outputs addressed by out_off, or NULL
  *   pstatus            device [P] output status words

@@ -78,6 +78,7 @@ const char *knit_status_string(int code) {
     case KNIT_P_SINGULAR: return "singular slice";
     case KNIT_P_NOCONV: return "decimation not converged";
     case KNIT_P_NONFINITE: return "non-finite value";
+    case KNIT_P_FALLBACK: return "refinement gave up; recomputed in FP64";
     default: return "combination of problem status bits or unknown code";
   }
 }
@@ -144,6 +145,14 @@ int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_proble
                        sweep_slab_bytes(Mmax, precision), Mmax, (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
+
+int knit_set_refine_threshold(double threshold) {
+  if (!(threshold >= 0.0)) return KNIT_E_ARG;   // also rejects NaN
+  sweep_set_refine_threshold(threshold);
+  return KNIT_OK;
+}
+
+double knit_get_refine_threshold(void) { return sweep_get_refine_threshold(); }
 
 int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tuning *t) {
   if (!precision_ok(precision) || cls < 0 || cls >= KNIT_TUNING_CLASSES) return KNIT_E_ARG;

@@ -53,6 +53,8 @@ constexpr int SWEEP_MAX_GRID = 512;   // upper bound of resident sweep workgroup
 
 bool sweep_mfma_supports(int Mmax);
 int sweep_tuning_set(int precision, int cls, const knit_sweep_tuning *t);
+int sweep_set_refine_threshold(double t);
+double sweep_get_refine_threshold();
 knit_sweep_tuning sweep_tuning_get(int precision, int Mpmax);
 knit_sweep_tuning sweep_default_tuning(int Mpmax);
 bool sweep_tuning_valid(int Mpmax, const knit_sweep_tuning &t);

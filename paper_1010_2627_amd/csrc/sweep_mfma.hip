@@ -26,6 +26,7 @@
 //                the product in FP64, then [g_n; G_1n] = [X0; G0] (I + R) with
 //                the correction product in FP32.
 
+#include <atomic>
 #include <mutex>
 
 #include "knit_internal.h"
@@ -73,6 +74,29 @@ __device__ __forceinline__ void wg_argmax_key(double v, int idx, unsigned int *k
   }
   vbest = bl ? __uint_as_float(bh) : -1.0f;
   ibest = bl ? (int)(0xffffffffu - bl) : 0x7fffffff;
+}
+
+// Workgroup maximum of a double, NaN if any thread holds NaN.  sv: one slot per
+// wave; ends with a barrier, so sv is free again on return.
+__device__ __forceinline__ double wg_max_nan(double v, double *sv) {
+  double nanflag = (v != v) ? 1.0 : 0.0;
+  double m = (v != v) ? 0.0 : v;
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off, 64));
+    nanflag = fmax(nanflag, __shfl_xor(nanflag, off, 64));
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sv[threadIdx.x >> 6] = nanflag > 0.0 ? -1.0 : m;
+  __syncthreads();
+  double r = 0.0;
+  bool nan = false;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    const double x = sv[w];
+    if (x < 0.0) nan = true;
+    else r = fmax(r, x);
+  }
+  __syncthreads();
+  return nan ? __builtin_nan("") : r;
 }
 
 // Rows of X are addressed through a logical -> physical map: pivoting permutes
@@ -493,7 +517,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
                                                         const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
                                                         knit_z *GNN, int32_t *pstatus, char *ws,
                                                         size_t slab_bytes, int Mpmax, unsigned int *queue,
-                                                        const int *order) {
+                                                        const int *order, double refine_tol, const int32_t *redo) {
   __shared__ int next_p;
   __shared__ int qa[NT], qb[NT];        // row order of the current / previous elimination
   __shared__ int pa[NT], pb[NT];        // and its inverse (column order of the inverse)
@@ -528,6 +552,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
     __syncthreads();
     if (pi >= P) break;
     const int p = order[pi];
+    // second pass of a refined sweep: only the problems the first pass gave up on
+    if (redo && !(redo[p] & KNIT_P_FALLBACK)) continue;
     const knit_problem pr = probs[p];
     const StripDev s = tab.s[pr.strip];
     const int M = s.M, no = s.norb, L = pr.L;
@@ -567,11 +593,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
           Xn[i] = cvt<float>(X[(int64_t)(a < Mp ? q[a] : a) * Mp + pinv[b]]);
         }
         __syncthreads();
-        // residual R = I - A_n X0, FP64 product
+        // residual R = I - A_n X0, FP64 product, and its largest entry
+        double rmax = 0.0;
         wg_gemm_mfma<double>(Mp, Mp, Mp, A64, Mp, Xn, Mp, [&](int r, int c, double &re, double &im) {
-          Rr[(int64_t)r * Mp + c] = cpx<float>{(float)((r == c ? 1.0 : 0.0) - re), (float)(-im)};
+          const double rr = (r == c ? 1.0 : 0.0) - re, ri = -im;
+          const double a = fabs(rr) + fabs(ri);
+          rmax = (a != a || rmax != rmax) ? __builtin_nan("") : fmax(rmax, a);
+          Rr[(int64_t)r * Mp + c] = cpx<float>{(float)rr, (float)ri};
         });
-        __syncthreads();
+        rmax = wg_max_nan(rmax, sv);
+        // one step leaves a relative error ~ |R|^2: beyond the threshold (or on a
+        // diverging inverse) the problem is handed to the FP64 pass
+        if (!(rmax <= refine_tol)) {
+          flags |= KNIT_P_FALLBACK;
+          break;
+        }
         // [g; G1] = [X0; G0] + [X0; G0] R, correction in FP32
         wg_gemm_mfma<float>(R, Mp, Mp, Xn, Mp, Rr, Mp, [&](int r, int c, float &re, float &im) {
           const int64_t o = (int64_t)r * Mp + c;
@@ -615,32 +651,36 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
       int *t2 = pinv; pinv = pinvp; pinvp = t2;
       cpx<RG> *t3 = X; X = Xp; Xp = t3;
     }
-    // outputs (the leading M x M blocks)
-    double bad = 0.0;
-    const int64_t mm = (int64_t)M * M;
-    for (int64_t i = tid; i < mm; i += nt) {
-      const int a = (int)(i / M), b = (int)(i % M);
-      const int64_t o = (int64_t)a * Mp + b;
-      bad = fmax(bad, c_abs1(G1[o]));
-      if (GNN) bad = fmax(bad, c_abs1(g[o]));
-      if (want_n1) bad = fmax(bad, c_abs1(N1a[o]));
-    }
-    if (bad != bad) bad = INFINITY;
-    for (int off = 32; off > 0; off >>= 1) bad = fmax(bad, __shfl_xor(bad, off, 64));
-    if ((tid & 63) == 0) sv[tid >> 6] = bad;
-    __syncthreads();
-    bad = sv[0];
-    for (int w = 1; w < (nt >> 6); ++w) bad = fmax(bad, sv[w]);
-    __syncthreads();
-    if (!isfinite(bad)) flags |= KNIT_P_NONFINITE;
-    const bool kill = (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) != 0;
-    const cpx<double> nanz = {qnan, qnan};
-    for (int64_t i = tid; i < mm; i += nt) {
-      const int a = (int)(i / M), b = (int)(i % M);
-      const int64_t o = (int64_t)a * Mp + b;
-      st_z(G1N + pr.out_off + i, kill ? nanz : cvt<double>(G1[o]));
-      if (GNN) st_z(GNN + pr.out_off + i, kill ? nanz : cvt<double>(g[o]));
-      if (want_n1) st_z(GN1 + pr.out_off + i, kill ? nanz : cvt<double>(N1a[o]));
+    // outputs (the leading M x M blocks); a problem the refined pass gave up on
+    // only records that, the FP64 pass writes its outputs
+    if (redo) flags |= KNIT_P_FALLBACK;
+    if (redo || !(flags & KNIT_P_FALLBACK)) {
+      double bad = 0.0;
+      const int64_t mm = (int64_t)M * M;
+      for (int64_t i = tid; i < mm; i += nt) {
+        const int a = (int)(i / M), b = (int)(i % M);
+        const int64_t o = (int64_t)a * Mp + b;
+        bad = fmax(bad, c_abs1(G1[o]));
+        if (GNN) bad = fmax(bad, c_abs1(g[o]));
+        if (want_n1) bad = fmax(bad, c_abs1(N1a[o]));
+      }
+      if (bad != bad) bad = INFINITY;
+      for (int off = 32; off > 0; off >>= 1) bad = fmax(bad, __shfl_xor(bad, off, 64));
+      if ((tid & 63) == 0) sv[tid >> 6] = bad;
+      __syncthreads();
+      bad = sv[0];
+      for (int w = 1; w < (nt >> 6); ++w) bad = fmax(bad, sv[w]);
+      __syncthreads();
+      if (!isfinite(bad)) flags |= KNIT_P_NONFINITE;
+      const bool kill = (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) != 0;
+      const cpx<double> nanz = {qnan, qnan};
+      for (int64_t i = tid; i < mm; i += nt) {
+        const int a = (int)(i / M), b = (int)(i % M);
+        const int64_t o = (int64_t)a * Mp + b;
+        st_z(G1N + pr.out_off + i, kill ? nanz : cvt<double>(G1[o]));
+        if (GNN) st_z(GNN + pr.out_off + i, kill ? nanz : cvt<double>(g[o]));
+        if (want_n1) st_z(GN1 + pr.out_off + i, kill ? nanz : cvt<double>(N1a[o]));
+      }
     }
     if (tid == 0) pstatus[p] = flags;
     __syncthreads();
@@ -721,10 +761,30 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
 // 256 bytes), then one slab per workgroup.
 static size_t order_bytes(int P) { return (((size_t)P * sizeof(int)) + 255) & ~size_t(255); }
 
+// The refined sweep's second (FP64) pass shares the workspace.
+static size_t slab_for(int Mmax, int precision) {
+  size_t s = sweep_mfma_slab_bytes(Mmax, precision);
+  if (precision == KNIT_FP32_REFINE) {
+    const size_t s64 = sweep_mfma_slab_bytes(Mmax, KNIT_FP64);
+    if (s64 > s) s = s64;
+  }
+  return s;
+}
+
 size_t sweep_mfma_workspace(int Mmax, int precision, int P) {
   const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
-  return 256 + order_bytes(P) + sweep_mfma_slab_bytes(Mmax, precision) * (size_t)grid;
+  return 256 + order_bytes(P) + slab_for(Mmax, precision) * (size_t)grid;
 }
+
+namespace {
+std::atomic<double> refine_threshold{1e-3};
+}
+
+int sweep_set_refine_threshold(double t) {
+  refine_threshold.store(t);
+  return 0;
+}
+double sweep_get_refine_threshold() { return refine_threshold.load(); }
 
 // Launch tuning per (precision, padded-slice class), set by the autotuner.
 namespace {
@@ -776,34 +836,41 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
   unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
   int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
   char *w = reinterpret_cast<char *>(ws) + 256 + order_bytes(P);
-  const size_t slab = sweep_mfma_slab_bytes(Mmax, precision);
   const int Mpmax = mfma_padded(Mmax);
-  // workgroup size, workgroups per compute unit and queue order from the
-  // tuning table (default: 256 threads, two per compute unit, when the padded
-  // slice fits one panel row per thread, else 512 threads, one per unit; LPT)
-  const knit_sweep_tuning tune = sweep_tuning_get(precision, Mpmax);
-  const bool small = tune.threads == 256;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  int grid = tune.wg_per_cu * ncu;
-  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
-  if (grid > P) grid = P;
-  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
+  const double rtol = sweep_get_refine_threshold();
+  // one pass at `prec`; redo != NULL restricts it to the problems flagged KNIT_P_FALLBACK
+  auto pass = [&](int prec, const int32_t *redo) -> hipError_t {
+    // workgroup size, workgroups per compute unit and queue order from the
+    // tuning table (default: 256 threads, two per compute unit, when the padded
+    // slice fits one panel row per thread, else 512 threads, one per unit; LPT)
+    const knit_sweep_tuning tune = sweep_tuning_get(prec, Mpmax);
+    const bool small = tune.threads == 256;
+    const size_t slab = sweep_mfma_slab_bytes(Mmax, prec);
+    int grid = tune.wg_per_cu * ncu;
+    if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+    if (grid > P) grid = P;
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
 #define KNIT_LAUNCH(RG, RS, RF, NT)                                                                          \
   hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, \
-                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order)
-  if (precision == KNIT_FP64) {
-    if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
-  } else if (precision == KNIT_FP32) {
-    if (small) KNIT_LAUNCH(float, float, false, 256); else KNIT_LAUNCH(float, float, false, 512);
-  } else {
-    if (small) KNIT_LAUNCH(float, double, true, 256); else KNIT_LAUNCH(float, double, true, 512);
-  }
+                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order, rtol, redo)
+    if (prec == KNIT_FP64) {
+      if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
+    } else if (prec == KNIT_FP32) {
+      if (small) KNIT_LAUNCH(float, float, false, 256); else KNIT_LAUNCH(float, float, false, 512);
+    } else {
+      if (small) KNIT_LAUNCH(float, double, true, 256); else KNIT_LAUNCH(float, double, true, 512);
+    }
 #undef KNIT_LAUNCH
-  return hipGetLastError();
+    return hipGetLastError();
+  };
+  hipError_t err = pass(precision, nullptr);
+  if (err != hipSuccess || precision != KNIT_FP32_REFINE) return err;
+  return pass(KNIT_FP64, pstatus);
 }
 
 }  // namespace knit

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libknit.so")
 
 KNIT_OK, KNIT_E_ARG, KNIT_E_DEVICE, KNIT_E_WORKSPACE, KNIT_E_UNSUPPORTED = 0, -1, -2, -3, -4
-KNIT_P_OK, KNIT_P_SINGULAR, KNIT_P_NOCONV, KNIT_P_NONFINITE = 0, 1, 2, 4
+KNIT_P_OK, KNIT_P_SINGULAR, KNIT_P_NOCONV, KNIT_P_NONFINITE, KNIT_P_FALLBACK = 0, 1, 2, 4, 8
 KNIT_FP64, KNIT_FP32_REFINE, KNIT_FP32 = 0, 1, 2
 PRECISIONS = {"fp64": KNIT_FP64, "fp32_refine": KNIT_FP32_REFINE, "fp32": KNIT_FP32}
 KNIT_MAX_STRIPS = 64
@@ -76,7 +76,12 @@ _lib.knit_sweep_tuning_set.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTun
 _lib.knit_sweep_tuning_get.restype = c_i32
 _lib.knit_sweep_tuning_get.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTuning)]
 
-EXPORTED = ["knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
+_lib.knit_set_refine_threshold.restype = c_i32
+_lib.knit_set_refine_threshold.argtypes = [c_dbl]
+_lib.knit_get_refine_threshold.restype = c_dbl
+_lib.knit_get_refine_threshold.argtypes = []
+
+EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get"]
@@ -107,6 +112,16 @@ def knit_sweep_tuning_set(precision, cls: int, threads: int | None = None, wg_pe
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     t = None if threads is None else ctypes.byref(KnitSweepTuning(int(threads), int(wg_per_cu), int(order)))
     _check(_lib.knit_sweep_tuning_set(prec, int(cls), t), "knit_sweep_tuning_set")
+
+
+def knit_set_refine_threshold(threshold: float):
+    """Largest residual entry one FP32-refinement step may start from before the problem is
+    recomputed in FP64 (KNIT_P_FALLBACK)."""
+    _check(_lib.knit_set_refine_threshold(float(threshold)), "knit_set_refine_threshold")
+
+
+def knit_get_refine_threshold() -> float:
+    return float(_lib.knit_get_refine_threshold())
 
 
 def knit_sweep_tuning_get(precision, cls: int) -> dict:

@@ -198,3 +198,18 @@ def test_autotune_candidates_and_json(K, tmp_path):
         assert K.knit_sweep_tuning_get("fp64", 5) == {"threads": 512, "wg_per_cu": 1, "order": 0}
     finally:
         K.knit_sweep_tuning_set("fp64", 5, None)
+
+
+def test_refine_threshold_validation(K):
+    old = K.knit_get_refine_threshold()
+    try:
+        assert K._lib.knit_set_refine_threshold(-1.0) == K.KNIT_E_ARG
+        assert K._lib.knit_set_refine_threshold(float("nan")) == K.KNIT_E_ARG
+        assert K._lib.knit_set_refine_threshold(0.0) == K.KNIT_OK
+        assert K.knit_get_refine_threshold() == 0.0
+        assert K._lib.knit_set_refine_threshold(float("inf")) == K.KNIT_OK
+        K.knit_set_refine_threshold(0.25)
+        assert K.knit_get_refine_threshold() == 0.25
+    finally:
+        K.knit_set_refine_threshold(old)
+    assert K.status_string(K.KNIT_P_FALLBACK).startswith("refinement")

@@ -101,3 +101,45 @@ def test_generic_kernel_above_512():
     torch.cuda.synchronize()
     assert int(status.abs().sum()) == 0
     assert abs(float(T.cpu().numpy()[0]) - Tref[0]) < 1e-10 * max(1.0, abs(Tref[0]))
+
+
+@gpu
+def test_refine_fallback_everywhere_equals_fp64_bitwise():
+    """Threshold 0: every problem's refinement is refused, so the call's second (FP64) pass
+    recomputes all of them; outputs equal the FP64 sweep bit for bit, status says so."""
+    from paper_1010_2627_amd import knit as K, workload
+    b = workload.square_batch(40, 24, 2.0, 6, 2)
+    b.compute_sigmas()
+    G64, _, N64, s64 = b.sweep("fp64", gnn=True)
+    old = K.knit_get_refine_threshold()
+    try:
+        K.knit_set_refine_threshold(0.0)
+        Gm, _, Nm, sm = b.sweep("fp32_refine", gnn=True)
+        torch.cuda.synchronize()
+    finally:
+        K.knit_set_refine_threshold(old)
+    assert int(s64.abs().sum()) == 0
+    assert torch.all(sm == K.KNIT_P_FALLBACK)
+    assert torch.equal(Gm, G64) and torch.equal(Nm, N64)
+
+
+@gpu
+def test_refine_guard_bounds_the_error_on_strong_disorder():
+    """Strong disorder and many energies (slices far from well conditioned): problems the
+    guard hands to FP64 equal the FP64 sweep; the others stay within 1e-4 per open channel."""
+    from paper_1010_2627_amd import knit as K, workload
+    b = workload.square_batch(48, 96, 6.0, 48, 4, emin=-4.5, emax=4.5)
+    b.compute_sigmas()
+    G64, _, _, s64 = b.sweep("fp64", gnn=False)
+    T64 = b.transmission(G64)[0].cpu().numpy()
+    Gm, _, _, sm = b.sweep("fp32_refine", gnn=False)
+    Tm = b.transmission(Gm)[0].cpu().numpy()
+    sm = sm.cpu().numpy()
+    assert int(s64.abs().sum()) == 0
+    assert np.all((sm & ~K.KNIT_P_FALLBACK) == 0)
+    fb = (sm & K.KNIT_P_FALLBACK) != 0
+    assert np.array_equal(Tm[fb], T64[fb])
+    # channel count of the clean lead at each energy bounds T
+    nopen = np.maximum(1.0, np.ceil(np.abs(T64) - 1e-9))
+    err = np.abs(Tm - T64) / nopen
+    assert err[~fb].max(initial=0.0) <= 1e-4, (err.max(), int(fb.sum()))
