@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-The library must load, export every function include/knit.h declares, and
+The library must load, export every function include/knit.h and
+include/knit_mlp.h declare, and
 reject bad arguments on the host, before any HIP call, with KNIT_E_ARG or
 KNIT_E_WORKSPACE.  Device pointers passed here are fake, non-null addresses:
 every call below fails validation, so none is ever dereferenced.
@@ -26,8 +27,8 @@ def K():
     return knit
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "knit.h")).read()
+def _declared(header="knit.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(knit_[a-z_0-9]+)\s*\(", src)))
 
@@ -39,6 +40,16 @@ def test_library_exports_every_declared_symbol(K):
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(K.EXPORTED) == names
+
+
+def test_library_exports_every_sampler_kernel_entry(K):
+    from paper_1010_2627_amd import mlp
+    names = _declared("knit_mlp.h")
+    assert len(names) == 6
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(mlp.EXPORTED) == names
 
 
 def test_abi_version_and_status_strings(K):
@@ -213,3 +224,21 @@ def test_refine_threshold_validation(K):
     finally:
         K.knit_set_refine_threshold(old)
     assert K.status_string(K.KNIT_P_FALLBACK).startswith("refinement")
+
+
+def test_sampler_kernel_argument_checks(K):
+    lib = K._lib
+    from paper_1010_2627_amd import mlp  # noqa: F401  (sets the argument types)
+    assert lib.knit_mlp_gemm(-1, 4, 4, FAKE, 4, 1, FAKE, 4, 1, None, 0.0, FAKE, 4, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_gemm(4, 4, 4, FAKE, 4, 1, FAKE, 4, 1, None, 0.0, FAKE, 3, None) == K.KNIT_E_ARG   # ldc < N
+    assert lib.knit_mlp_gemm(4, 4, 4, None, 4, 1, FAKE, 4, 1, None, 0.0, FAKE, 4, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_gemm(0, 4, 4, None, 4, 1, None, 4, 1, None, 0.0, None, 4, None) == K.KNIT_OK
+    assert lib.knit_mlp_act_fwd(-1, FAKE, FAKE, 1, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_act_fwd(0, None, None, 1, None) == K.KNIT_OK
+    assert lib.knit_mlp_gelu_bwd(4, FAKE, None, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_softmax_xent(4, 8, None, FAKE, 1.0, FAKE, None, None, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_softmax_xent(4, 8, FAKE, None, 1.0, FAKE, None, None, None) == K.KNIT_E_ARG  # loss needs q
+    assert lib.knit_mlp_colsum(4, 8, None, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_adamw(4, FAKE, None, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.99, 1e-8, 0.0, 1, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_adamw(4, FAKE, None, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.99, 1e-8, 0.0, 0, None) == K.KNIT_E_ARG
+    assert lib.knit_mlp_adamw(4, FAKE, None, None, FAKE, FAKE, 1e-3, 0.9, 0.99, 1e-8, 0.0, 1, None) == K.KNIT_E_ARG

@@ -1,0 +1,128 @@
+"""CPU pins of the learned sampler's reference network and of the sampler's host logic.
+
+The reference (oracle.mlp) is checked against what fixes it independently: torch's own
+bfloat16 rounding, central finite differences of the exact (FP64, unrounded) network,
+and torch.optim.AdamW.  The sampler's placement and integration rules are checked on
+inputs whose answer is known in closed form.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as OM
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.Generator(np.random.PCG64(1))
+    x = np.concatenate([rng.normal(size=4000).astype(np.float32) * 10.0 ** rng.integers(-30, 30, 4000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 65504.0, 1e-40, -0.0,
+                                  np.inf, -np.inf, 3.3895314e38], np.float32)]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    got = OM.bf16_round(x)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def _tiny(seed=0, sizes=(5, 7, 6, 4)):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = [(rng.normal(size=(o, i)), rng.normal(size=o) * 0.1) for i, o in zip(sizes[:-1], sizes[1:])]
+    x = rng.normal(size=(3, sizes[0]))
+    q = rng.random(size=(3, sizes[-1]))
+    q /= q.sum(axis=1, keepdims=True)
+    return params, x, q
+
+
+def test_backward_matches_finite_differences_fp64():
+    params, x, q = _tiny()
+    logits, cache = OM.forward(params, x, rounding=False)
+    grads = OM.backward(params, cache, q)
+    h = 1e-6
+    for li, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[li][0]), (b, grads[li][1])):
+            fd = np.zeros_like(arr)
+            it = np.nditer(arr, flags=["multi_index"])
+            for _ in it:
+                i = it.multi_index
+                old = arr[i]
+                arr[i] = old + h
+                lp = OM.xent_loss(OM.forward(params, x, rounding=False)[0], q)
+                arr[i] = old - h
+                lm = OM.xent_loss(OM.forward(params, x, rounding=False)[0], q)
+                arr[i] = old
+                fd[i] = (lp - lm) / (2 * h)
+            assert np.linalg.norm(fd - g) <= 1e-6 * max(1.0, np.linalg.norm(fd)), (li, np.abs(fd - g).max())
+
+
+def test_gelu_and_its_derivative():
+    x = np.linspace(-6, 6, 2001)
+    from math import erf, sqrt, pi, exp
+    ref = np.array([0.5 * v * (1 + erf(v / sqrt(2))) for v in x])
+    assert np.allclose(OM.gelu(x), ref, atol=1e-15)
+    h = 1e-6
+    assert np.allclose(OM.gelu_grad(x), (OM.gelu(x + h) - OM.gelu(x - h)) / (2 * h), atol=1e-8)
+    assert OM.gelu(np.array([0.0]))[0] == 0.0 and abs(OM.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
+
+
+def test_adamw_matches_torch():
+    rng = np.random.Generator(np.random.PCG64(2))
+    w0 = rng.normal(size=50)
+    gs = [rng.normal(size=50) for _ in range(5)]
+    p = torch.nn.Parameter(torch.from_numpy(w0.copy()))
+    opt = torch.optim.AdamW([p], lr=3e-3, betas=(0.9, 0.99), eps=1e-8, weight_decay=0.05)
+    w, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    for t, g in enumerate(gs, start=1):
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        w, m, v = OM.adamw(w, g, m, v, t, 3e-3, 0.9, 0.99, 1e-8, 0.05)
+    assert np.allclose(w, p.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def test_rounded_network_stays_close_to_exact():
+    """BF16 rounding at the stated boundaries perturbs, but does not change, the gradients."""
+    params, x, q = _tiny(3, sizes=(16, 32, 32, 8))
+    l64, c64 = OM.forward(params, x, rounding=False)
+    l16, c16 = OM.forward([(W.astype(np.float32), b.astype(np.float32)) for W, b in params], x.astype(np.float32))
+    assert np.abs(l16 - l64).max() < 0.02 * np.abs(l64).max()      # bf16 keeps 8 significant bits
+    g64, g16 = OM.backward(params, c64, q), OM.backward(params, c16, q.astype(np.float32))
+    for (a, _), (b, _) in zip(g64, g16):
+        cos = float((a * b).sum() / np.linalg.norm(a) / np.linalg.norm(b))
+        assert cos > 0.99
+
+
+# ---------------------------------------------------------------- sampler host logic
+
+def test_placement_of_a_uniform_density_is_the_midpoint_grid():
+    from paper_1010_2627_amd import sampler as S
+    E = S.place(np.full(S.N_BINS, 1.0 / S.N_BINS))
+    assert np.allclose(E, S.midpoints(S.N_LEARNED), atol=1e-12)
+
+
+def test_placement_follows_the_density():
+    from paper_1010_2627_amd import sampler as S
+    p = np.zeros(S.N_BINS)
+    p[100] = 1.0
+    E = S.place(p)
+    width = (S.EMAX - S.EMIN) / S.N_BINS
+    inside = (E >= S.EMIN + 100 * width) & (E <= S.EMIN + 101 * width)
+    # 80% of the mass sits in bin 100 (plus its 0.2/512 share of the uniform part)
+    assert abs(inside.sum() - 0.8 * S.N_LEARNED) <= 2
+    assert np.all(np.diff(E) >= 0)
+    assert S.place(np.full(S.N_BINS, np.nan)) is None        # unusable density -> caller falls back
+    assert np.all(np.abs(S.place(np.eye(S.N_BINS)[256])) >= 1e-5)   # never on the zigzag flat band
+
+
+def test_trapezoid_is_exact_for_piecewise_linear_functions():
+    from paper_1010_2627_amd import sampler as S
+    rng = np.random.Generator(np.random.PCG64(4))
+    E = np.concatenate([[S.EMIN, S.EMAX], rng.uniform(S.EMIN, S.EMAX, 50)])
+    assert abs(S.integrate(E, 2.0 * E + 1.0) - 6.0) < 1e-12      # int_{-3}^{3} (2E+1) dE = 6
+
+
+def test_target_density_is_flat_for_linear_and_peaks_at_a_kink():
+    from paper_1010_2627_amd import sampler as S
+    E = S.midpoints(S.N_BINS)
+    q = S.target_density(3.0 * E + 2.0)
+    assert np.allclose(q, 1.0 / S.N_BINS, rtol=1e-6)
+    q = S.target_density(np.abs(E - 0.5))
+    k = np.argmin(np.abs(E - 0.5))
+    assert q.argmax() in (k - 1, k, k + 1) and q.max() > 10 * np.median(q)
