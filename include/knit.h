@@ -173,6 +173,8 @@ int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E,
  *              so threads >= Mp)
  *   wg_per_cu  resident workgroups per compute unit the grid is sized for (1, 2)
  *   order      0: problems in table order; 1: longest (Mp^3 L) first
+ *   outer      outer panel width of the blocked elimination, 64 or 128 (each
+ *              outer panel is one read-and-write pass over the slice matrix)
  *
  * Process-wide; set before the sweeps that should use it (calls that run
  * concurrently with a change see either the old or the new entry).
@@ -183,6 +185,7 @@ typedef struct knit_sweep_tuning {
   int32_t threads;
   int32_t wg_per_cu;
   int32_t order;
+  int32_t outer;
 } knit_sweep_tuning;
 
 int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tuning *t);

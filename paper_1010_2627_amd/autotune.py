@@ -1,6 +1,6 @@
 """Autotuner for the batched matrix-core sweep's launch shape.
 
-The persistent sweep kernel has three launch knobs, kept per precision and
+The persistent sweep kernel has four launch knobs, kept per precision and
 padded-slice class in the library's tuning table (``knit_sweep_tuning_set``):
 
 * threads per workgroup, 256 or 512. One panel row per thread, so at least
@@ -9,6 +9,9 @@ padded-slice class in the library's tuning table (``knit_sweep_tuning_set``):
   problems share a compute unit and hide each other's barrier latency.
 * queue order: the problem table's order, or longest-processing-time first
   on the cost Mp³·L.
+* outer panel width of the blocked elimination, 64 or 128. Each outer panel
+  is one pass over the slice matrix in memory; wider panels make fewer passes
+  but a longer restricted elimination inside each.
 
 ``tune_batch`` times every valid candidate on a sample of a batch and
 installs the fastest. The sample is the batch's own problems with each strip
@@ -32,10 +35,10 @@ from . import knit as K
 def candidates(Mp: int):
     """Every valid tuning entry for padded slice size Mp."""
     out = []
-    for threads, wg, order in itertools.product((256, 512), (1, 2), (0, 1)):
-        if threads < Mp:
+    for threads, wg, order, outer in itertools.product((256, 512), (1, 2), (0, 1), (64, 128)):
+        if threads < Mp or outer > Mp:
             continue
-        out.append({"threads": threads, "wg_per_cu": wg, "order": order})
+        out.append({"threads": threads, "wg_per_cu": wg, "order": order, "outer": outer})
     return out
 
 
@@ -107,6 +110,7 @@ def load(path: str) -> int:
     n = 0
     for prec, entries in table.items():
         for cls, e in entries.items():
-            K.knit_sweep_tuning_set(prec, int(cls), int(e["threads"]), int(e["wg_per_cu"]), int(e["order"]))
+            K.knit_sweep_tuning_set(prec, int(cls), int(e["threads"]), int(e["wg_per_cu"]), int(e["order"]),
+                                    int(e.get("outer", 64)))
             n += 1
     return n

@@ -38,6 +38,7 @@ namespace knit {
 namespace {
 
 constexpr int MPAD = 32;   // slice dimension padding
+constexpr int NO_MAX = 128;  // widest outer panel (scratch is sized for it)
 // inner panel width = wave tile edge of the inner phases
 template <class RG> struct PanelW;
 template <> struct PanelW<double> { static constexpr int NB = 16; };
@@ -234,7 +235,9 @@ __device__ __attribute__((noinline)) void tile_gemm_window_flat(
     else
       acc.zero();
     // operands in double-buffered chunks of CH k-slices: the loads of chunk
-    // c + 1 are in flight while the MFMAs of chunk c run
+    // c + 1 are in flight while the MFMAs of chunk c run.  KT > 0: K = KT,
+    // fully unrolled; KT == 0: K is a runtime multiple of 8 CH, walked in
+    // pairs of chunks so that both buffers keep static indices
     constexpr int CH = NBLK == 1 ? 4 : 2, NCH = KT / 4 / CH;
     cpx<RG> a[2][CH][NBLK], b[2][CH][NBLK];
     auto load = [&](int ch, int buf) {
@@ -249,11 +252,24 @@ __device__ __attribute__((noinline)) void tile_gemm_window_flat(
       }
     };
     load(0, 0);
+    if constexpr (KT > 0) {
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      if (ch + 1 < NCH) load(ch + 1, (ch + 1) & 1);
+      for (int ch = 0; ch < NCH; ++ch) {
+        if (ch + 1 < NCH) load(ch + 1, (ch + 1) & 1);
 #pragma unroll
-      for (int q2 = 0; q2 < CH; ++q2) ctile_mma<RG, NBLK>(acc, a[ch & 1][q2], b[ch & 1][q2]);
+        for (int q2 = 0; q2 < CH; ++q2) ctile_mma<RG, NBLK>(acc, a[ch & 1][q2], b[ch & 1][q2]);
+      }
+    } else {
+      const int nch = K / (4 * CH);   // even
+#pragma unroll 1
+      for (int ch = 0; ch < nch; ch += 2) {
+        load(ch + 1, 1);
+#pragma unroll
+        for (int q2 = 0; q2 < CH; ++q2) ctile_mma<RG, NBLK>(acc, a[0][q2], b[0][q2]);
+        if (ch + 2 < nch) load(ch + 2, 0);
+#pragma unroll
+        for (int q2 = 0; q2 < CH; ++q2) ctile_mma<RG, NBLK>(acc, a[1][q2], b[1][q2]);
+      }
     }
     ctile_for_each<RG, NBLK>(acc, [=](int r, int c, RG &re, RG &im) {
       *dst_of(r, c) = negate ? cpx<RG>{-re, -im} : cpx<RG>{re, im};
@@ -271,22 +287,22 @@ __device__ __forceinline__ void tile_gemm_window(const cpx<RG> *X, cpx<RG> *S, i
                                       rows.hole, rows.hole_len, cols.base1, cols.n1, cols.base2, cols.n,         \
                                       cols.hole, cols.hole_len, K, arow, acol, krow0, bshift, fl)
   if (NBLK == 1) KNIT_TGW(16);            // inner panels: K = 16
-  else if (K == 64) KNIT_TGW(64);         // outer panels
-  else KNIT_TGW(32);                      // last outer panel of a 32-padded slice
+  else if (K == 64) KNIT_TGW(64);         // outer panels of 64
+  else KNIT_TGW(0);                       // any other multiple of 32 (runtime K)
 #undef KNIT_TGW
 }
 
 // Gauss-Jordan with partial pivoting in two levels: outer panels of NO columns
-// (NO = 64, the last one may be 32 wide) whose restricted elimination runs as
+// (NO = 64 or 128, the last one may be narrower by multiples of 32) whose
+// restricted elimination runs as
 // NI = PanelW steps confined to the outer panel's columns and to the logical
 // rows [K0, Mp); then one rank-NO update of the rest of the matrix.  The whole
 // matrix is touched once per outer panel instead of once per inner panel.
 // Sb ([R][NO]) and Sd ([NO][Mp]) hold the two products that cannot be formed
 // in place.  phys (LDS, Mp entries) receives the final row order.
-template <class RG, int NT, int NI = PanelW<RG>::NB>
+template <class RG, int NT, int NO, int NI = PanelW<RG>::NB>
 __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg, cpx<RG> *prow, double *sv,
                             int *si, cpx<RG> *Sb, cpx<RG> *Sd) {
-  constexpr int NO = 64;
   constexpr int BI = NI / 16;      // inner tile blocks
   for (int i = threadIdx.x; i < Mp; i += blockDim.x) phys[i] = i;
   __syncthreads();
@@ -517,7 +533,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
                                                         const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
                                                         knit_z *GNN, int32_t *pstatus, char *ws,
                                                         size_t slab_bytes, int Mpmax, unsigned int *queue,
-                                                        const int *order, double refine_tol, const int32_t *redo) {
+                                                        const int *order, double refine_tol, const int32_t *redo,
+                                                        int outer) {
   __shared__ int next_p;
   __shared__ int qa[NT], qb[NT];        // row order of the current / previous elimination
   __shared__ int pa[NT], pb[NT];        // and its inverse (column order of the inverse)
@@ -538,8 +555,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
   cpx<double> *A64 = reinterpret_cast<cpx<double> *>(N1b + EE);   // [Mp][Mp]   (REFINE)
   cpx<float> *Xn = reinterpret_cast<cpx<float> *>(A64 + (REFINE ? EE : 0));   // [2 Mp][Mp] (REFINE)
   cpx<float> *Rr = Xn + (REFINE ? 2 * EE : 0);                    // [Mp][Mp]   (REFINE)
-  cpx<RG> *Sb = reinterpret_cast<cpx<RG> *>(Rr + (REFINE ? EE : 0));   // [2 Mp][64] scratch
-  cpx<RG> *Sd = Sb + (int64_t)2 * Mpmax * 64;                           // [64][Mp]   scratch
+  cpx<RG> *Sb = reinterpret_cast<cpx<RG> *>(Rr + (REFINE ? EE : 0));   // [2 Mp][NO] scratch
+  cpx<RG> *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;                       // [NO][Mp]   scratch
   const bool want_n1 = GN1 != nullptr;
   const double qnan = __builtin_nan("");
 
@@ -582,7 +599,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
       }
       __syncthreads();
       const int R = n > 0 ? 2 * Mp : Mp;
-      flags |= gj_two_level<RG, NT>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd);
+      flags |= outer == 128 ? gj_two_level<RG, NT, 128>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd)
+                            : gj_two_level<RG, NT, 64>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd);
       for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
       __syncthreads();
       // logical row a of the result sits in physical row q[a] (a < Mp)
@@ -707,8 +725,9 @@ inverse_fp64_kernel(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64
   if (skip && skip[(int64_t)e * skip_stride]) return;
   cpx<double> *Xe = X + (int64_t)e * xstride;
   cpx<double> *Sb = scratch + (int64_t)e * sstride;
-  cpx<double> *Sd = Sb + (int64_t)2 * Mp * 64;
-  const int fl = gj_two_level<double, NT>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
+  cpx<double> *Sd = Sb + (int64_t)2 * Mp * NO_MAX;
+  const int fl = Mp >= 384 ? gj_two_level<double, NT, 128>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
+                           : gj_two_level<double, NT, 64>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
   for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
   __syncthreads();
   cpx<double> *o = out + (int64_t)e * ostride;
@@ -731,7 +750,7 @@ size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
   if (precision == KNIT_FP64) b = EE * (4 * 16 + 4 * 16);
   else if (precision == KNIT_FP32) b = EE * (4 * 8 + 4 * 8);
   else b = EE * (4 * 8 + 4 * 16 + 16 + 2 * 8 + 8);
-  b += (2 * Mp * 64 + 64 * Mp) * gs;                      // Sb, Sd scratch
+  b += (2 * Mp * NO_MAX + NO_MAX * Mp) * gs;              // Sb, Sd scratch
   return (b + 255) & ~size_t(255);
 }
 
@@ -739,7 +758,7 @@ bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= 512; }
 
 size_t inverse_fp64_scratch_elems(int M) {
   const size_t Mp = (size_t)mfma_padded(M);
-  return 2 * Mp * 64 + 64 * Mp;
+  return 2 * Mp * NO_MAX + NO_MAX * Mp;
 }
 
 hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64_t sstride, int M,
@@ -798,6 +817,7 @@ knit_sweep_tuning sweep_default_tuning(int Mpmax) {
   t.threads = Mpmax <= 256 ? 256 : 512;
   t.wg_per_cu = Mpmax <= 256 ? 2 : 1;
   t.order = 1;
+  t.outer = Mpmax >= 384 ? 128 : 64;
   return t;
 }
 
@@ -806,6 +826,7 @@ bool sweep_tuning_valid(int Mpmax, const knit_sweep_tuning &t) {
   if (t.threads < Mpmax) return false;                 // one panel row per thread
   if (t.wg_per_cu < 1 || t.wg_per_cu > 2) return false;
   if (t.order != 0 && t.order != 1) return false;
+  if (t.outer != 64 && t.outer != 128) return false;
   return true;
 }
 
@@ -857,7 +878,7 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
     hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
 #define KNIT_LAUNCH(RG, RS, RF, NT)                                                                          \
   hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, \
-                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order, rtol, redo)
+                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order, rtol, redo, tune.outer)
     if (prec == KNIT_FP64) {
       if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
     } else if (prec == KNIT_FP32) {

@@ -67,7 +67,7 @@ _lib.knit_ldos.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i3
 
 
 class KnitSweepTuning(ctypes.Structure):
-    _fields_ = [("threads", c_i32), ("wg_per_cu", c_i32), ("order", c_i32)]
+    _fields_ = [("threads", c_i32), ("wg_per_cu", c_i32), ("order", c_i32), ("outer", c_i32)]
 
 
 KNIT_TUNING_CLASSES = 16
@@ -107,10 +107,11 @@ def tuning_class(Mp: int) -> int:
 
 
 def knit_sweep_tuning_set(precision, cls: int, threads: int | None = None, wg_per_cu: int = 1,
-                          order: int = 1):
+                          order: int = 1, outer: int = 64):
     """Set (or, with threads=None, reset to the default) one entry of the sweep tuning table."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    t = None if threads is None else ctypes.byref(KnitSweepTuning(int(threads), int(wg_per_cu), int(order)))
+    t = None if threads is None else ctypes.byref(KnitSweepTuning(int(threads), int(wg_per_cu), int(order),
+                                                                   int(outer)))
     _check(_lib.knit_sweep_tuning_set(prec, int(cls), t), "knit_sweep_tuning_set")
 
 
@@ -128,7 +129,7 @@ def knit_sweep_tuning_get(precision, cls: int) -> dict:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     t = KnitSweepTuning()
     _check(_lib.knit_sweep_tuning_get(prec, int(cls), ctypes.byref(t)), "knit_sweep_tuning_get")
-    return {"threads": t.threads, "wg_per_cu": t.wg_per_cu, "order": t.order}
+    return {"threads": t.threads, "wg_per_cu": t.wg_per_cu, "order": t.order, "outer": t.outer}
 
 
 def _ptr(t) -> int | None:

@@ -174,39 +174,42 @@ def test_sweep_tuning_table_round_trip(K):
     f_set, f_get = K._lib.knit_sweep_tuning_set, K._lib.knit_sweep_tuning_get
     T = K.KnitSweepTuning
     out = T()
-    # defaults: 256 threads and two workgroups per unit up to Mp = 256, then 512 threads, one per unit
+    # defaults: 256 threads and two workgroups per unit up to Mp = 256, then 512 threads, one per
+    # unit; outer panels of 64 below Mp = 384, else 128
     assert f_get(K.KNIT_FP64, 3, ctypes.byref(out)) == K.KNIT_OK            # Mp = 128
-    assert (out.threads, out.wg_per_cu, out.order) == (256, 2, 1)
+    assert (out.threads, out.wg_per_cu, out.order, out.outer) == (256, 2, 1, 64)
     assert f_get(K.KNIT_FP64, 15, ctypes.byref(out)) == K.KNIT_OK           # Mp = 512
-    assert (out.threads, out.wg_per_cu, out.order) == (512, 1, 1)
+    assert (out.threads, out.wg_per_cu, out.order, out.outer) == (512, 1, 1, 128)
     # bad arguments
-    assert f_set(7, 3, ctypes.byref(T(256, 1, 0))) == K.KNIT_E_ARG           # precision
-    assert f_set(K.KNIT_FP64, 16, ctypes.byref(T(512, 1, 0))) == K.KNIT_E_ARG  # class
-    assert f_set(K.KNIT_FP64, -1, ctypes.byref(T(512, 1, 0))) == K.KNIT_E_ARG
-    assert f_set(K.KNIT_FP64, 8, ctypes.byref(T(256, 1, 0))) == K.KNIT_E_ARG   # Mp = 288 > 256 threads
-    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(384, 1, 0))) == K.KNIT_E_ARG
-    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(256, 3, 0))) == K.KNIT_E_ARG
-    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(256, 1, 2))) == K.KNIT_E_ARG
+    assert f_set(7, 3, ctypes.byref(T(256, 1, 0, 64))) == K.KNIT_E_ARG           # precision
+    assert f_set(K.KNIT_FP64, 16, ctypes.byref(T(512, 1, 0, 64))) == K.KNIT_E_ARG  # class
+    assert f_set(K.KNIT_FP64, -1, ctypes.byref(T(512, 1, 0, 64))) == K.KNIT_E_ARG
+    assert f_set(K.KNIT_FP64, 8, ctypes.byref(T(256, 1, 0, 64))) == K.KNIT_E_ARG   # Mp = 288 > 256 threads
+    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(384, 1, 0, 64))) == K.KNIT_E_ARG
+    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(256, 3, 0, 64))) == K.KNIT_E_ARG
+    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(256, 1, 2, 64))) == K.KNIT_E_ARG
+    assert f_set(K.KNIT_FP64, 3, ctypes.byref(T(256, 1, 0, 96))) == K.KNIT_E_ARG   # outer width
     assert f_get(K.KNIT_FP64, 3, None) == K.KNIT_E_ARG
     # round trip, then reset to the default
-    assert f_set(K.KNIT_FP32_REFINE, 3, ctypes.byref(T(512, 1, 0))) == K.KNIT_OK
-    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 512, "wg_per_cu": 1, "order": 0}
-    assert K.knit_sweep_tuning_get("fp64", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1}
+    assert f_set(K.KNIT_FP32_REFINE, 3, ctypes.byref(T(512, 1, 0, 128))) == K.KNIT_OK
+    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 512, "wg_per_cu": 1, "order": 0, "outer": 128}
+    assert K.knit_sweep_tuning_get("fp64", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 64}
     K.knit_sweep_tuning_set("fp32_refine", 3, None)
-    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1}
+    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 64}
 
 
 def test_autotune_candidates_and_json(K, tmp_path):
     from paper_1010_2627_amd import autotune
     assert all(c["threads"] >= 288 for c in autotune.candidates(288))
-    assert len(autotune.candidates(128)) == 8 and len(autotune.candidates(512)) == 4
-    tuned = [{"precision": "fp64", "cls": 5, "Mp": 192, "best": {"threads": 512, "wg_per_cu": 1, "order": 0},
-              "results": [({"threads": 512, "wg_per_cu": 1, "order": 0}, 0.5)]}]
+    assert len(autotune.candidates(128)) == 16 and len(autotune.candidates(512)) == 8
+    assert len(autotune.candidates(64)) == 8                     # no 128-wide outer panel in a 64 slice
+    best = {"threads": 512, "wg_per_cu": 1, "order": 0, "outer": 128}
+    tuned = [{"precision": "fp64", "cls": 5, "Mp": 192, "best": best, "results": [(best, 0.5)]}]
     path = str(tmp_path / "tuning.json")
     autotune.save(path, tuned)
     try:
         assert autotune.load(path) == 1
-        assert K.knit_sweep_tuning_get("fp64", 5) == {"threads": 512, "wg_per_cu": 1, "order": 0}
+        assert K.knit_sweep_tuning_get("fp64", 5) == best
     finally:
         K.knit_sweep_tuning_set("fp64", 5, None)
 
