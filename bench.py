@@ -65,6 +65,10 @@ WORKLOADS = {
                         "64 energies x 8 seeds = 512 problems"),
     "c1": dict(kind="square", W=16, L=64, w=1.0, n_energies=64, n_seeds=1,
                desc="square-lattice strip W=16, L=64, disorder U[-0.5,0.5], 64 energies"),
+    "c3": dict(kind="uneven", n_strips=512, n_energies=32,
+               desc="uneven batch in one persistent launch: 512 square-lattice strips, W ~ U{32,64,..,256}, "
+                    "L ~ U[256,2048], disorder U[-w/2,w/2] with w ~ U[0.5,3], 32 midpoint energies in "
+                    "(-3.9,3.9) each = 16384 problems"),
 }
 
 
@@ -75,26 +79,28 @@ def progress(msg):
 
 def build_batch(cfg):
     from paper_1010_2627_amd import workload
+    if cfg["kind"] == "uneven":
+        return workload.uneven_batch(n_strips=cfg["n_strips"], n_energies=cfg["n_energies"])
     if cfg["kind"] == "square":
         return workload.square_batch(cfg["W"], cfg["L"], cfg["w"], cfg["n_energies"], cfg["n_seeds"])
     return workload.rashba_batch(cfg["W"], cfg["L"], cfg["w"], cfg["n_energies"], cfg["n_seeds"])
 
 
-def open_channels(cfg, b):
-    """N_open(E) of the lead: T of the clean strip (one slice between the two leads), GPU path,
-    with the batch's own self-energies."""
+def open_channels(b):
+    """N_open(E) of every problem's lead: T of the clean strip (one slice between the two
+    leads) of its strip class, on the GPU path, with the batch's own self-energies."""
     import torch
-    from paper_1010_2627_amd import workload
-    if cfg["kind"] == "square":
-        c = workload.square_batch(cfg["W"], 1, 0.0, 1, 1)
-    else:
-        c = workload.rashba_batch(cfg["W"], 1, 0.0, 1, 1)
-    c = workload.Batch(c.strips, c.realizations, [np.asarray(b.energies[0])])
+    from paper_1010_2627_amd import inputs, workload
+    reals = [workload.Realization(i, inputs.clean_onsite(st, 1)) for i, st in enumerate(b.strips)]
+    c = workload.Batch(b.strips, reals, [np.asarray(E) for E in b.energies])
     c.sigmaL, c.sigmaR = b.sigmaL, b.sigmaR
     G1N, _, _, _ = c.sweep("fp64", gnn=False)
-    T = c.transmission(G1N)[0]
+    T = np.rint(c.transmission(G1N)[0].cpu().numpy()).astype(np.int64)
     torch.cuda.synchronize()
-    return np.rint(T.cpu().numpy()).astype(np.int64)
+    per_class = {}
+    for p, (ri, ei) in enumerate(c.prob_meta):
+        per_class[(int(ri), int(ei))] = T[p]
+    return np.array([per_class[(b.realizations[int(ri)].strip, int(ei))] for ri, ei in b.prob_meta])
 
 
 def cpu_baseline(cfg, b, budget_s=20.0):
@@ -112,13 +118,14 @@ def cpu_baseline(cfg, b, budget_s=20.0):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:                                                  # pragma: no cover
         threads = os.cpu_count() or 1
-    st = b.strips[0]
+    r0 = b.realizations[0]
+    st = b.strips[r0.strip]
     V = st.V_dense()
-    E_all = np.asarray(b.energies[0])
+    E_all = np.asarray(b.energies[r0.strip])
     nE = 4 if st.M <= 256 else 2
     idx = np.linspace(0, len(E_all) - 1, nE).astype(int)
     E = E_all[idx]
-    on = b.realizations[0].onsite
+    on = r0.onsite
     L = on.shape[0]
     with_sigma = st.M <= 256
     t0 = time.perf_counter()
@@ -126,9 +133,10 @@ def cpu_baseline(cfg, b, budget_s=20.0):
         sL = np.stack([OL.sigma_modes(st.H0, V, e, "L") for e in E])
         sR = np.stack([OL.sigma_modes(st.H0, V, e, "R") for e in E])
     else:
-        M = st.M
-        sL = np.stack([b.sigmaL[int(i) * M * M:(int(i) + 1) * M * M].view(M, M).cpu().numpy() for i in idx])
-        sR = np.stack([b.sigmaR[int(i) * M * M:(int(i) + 1) * M * M].view(M, M).cpu().numpy() for i in idx])
+        M, base = st.M, b.sigma_base[r0.strip]
+        sl = [slice(base + int(i) * M * M, base + (int(i) + 1) * M * M) for i in idx]
+        sL = np.stack([b.sigmaL[k].view(M, M).cpu().numpy() for k in sl])
+        sR = np.stack([b.sigmaR[k].view(M, M).cpu().numpy() for k in sl])
     t_sigma = time.perf_counter() - t0 if with_sigma else 0.0
     # a bounded number of slices keeps the sample inside the time budget
     t1 = time.perf_counter()
@@ -158,6 +166,8 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the sweep's launch shapes on a sample of the batch first and use the best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -179,10 +189,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     b = build_batch(cfg)
-    M = b.strips[0].M
+    Ms = np.array([b.strips[int(s)].M for s in b.probs.host["strip"]], dtype=np.float64)
+    M = int(Ms.max())
     steps_per_pass = b.slice_steps()
-    flops_per_pass = 16.0 * M ** 3 * steps_per_pass
-    G1N = torch.empty(b.P * M * M, dtype=torch.complex128, device="cuda")
+    flops_per_pass = float(np.sum(16.0 * Ms ** 3 * b.probs.host["L"]))
+    G1N = torch.empty(int(np.sum(Ms ** 2)), dtype=torch.complex128, device="cuda")
     stream = torch.cuda.current_stream()
     wss = {}
 
@@ -219,7 +230,17 @@ def main():
         bad = int((status.cpu().numpy() != 0).sum()) + int((b.sigma_status.cpu().numpy() != 0).sum())
         return T.cpu().numpy(), wall, ph.mean(axis=0), bad
 
-    progress(f"workload {args.workload}: {b.P} problems, M={M}, {steps_per_pass} slice-steps per step")
+    progress(f"workload {args.workload}: {b.P} problems, M<={M}, {steps_per_pass} slice-steps per step")
+    tuning = None
+    if args.autotune:
+        from paper_1010_2627_amd import autotune
+        b.compute_sigmas()
+        tuning = {}
+        for prec in ("fp64",) if args.no_mixed else ("fp64", "fp32_refine"):
+            r = autotune.tune_batch(b, prec, sample_slices=32, max_problems=2048)
+            tuning[prec] = {"Mp": r["Mp"], "best": r["best"],
+                            "candidates_ms": [[c, round(t * 1e3, 2)] for c, t in r["results"]]}
+            progress(f"autotune {prec}: {r['best']}")
     for i in range(args.warmup):
         one_step("fp64")
         torch.cuda.synchronize()
@@ -227,7 +248,7 @@ def main():
     T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", args.steps)
     progress(f"fp64: {args.steps} timed step(s), {wall64:.2f} s/step (self-energies {ts64:.2f} s, "
              f"sweep {tw64:.2f} s, trace {tt64:.3f} s)")
-    nopen = np.tile(open_channels(cfg, b), len(b.realizations))
+    nopen = open_channels(b)
 
     achieved = flops_per_pass / tw64 / 1e12
     tr = MEASURED_TRAFFIC.get(args.workload)
@@ -245,7 +266,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": cfg["desc"], "slice_dim_M": M,
+        "config": {"workload": args.workload, "description": cfg["desc"], "slice_dim_M_max": M,
                    "problems": b.P, "slice_steps_per_step": steps_per_pass,
                    "headline_precision": "fp64 (the path meeting the T tolerance at every point)"},
         "phases_s": {"lead_selfenergy_dd": round(float(ts64), 4), "sweep": round(float(tw64), 4),
@@ -281,6 +302,8 @@ def main():
             "problems_with_status": badm,
         }
     out["n_open_range"] = [int(nopen.min()), int(nopen.max())]
+    if tuning is not None:
+        out["autotune"] = tuning
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, b)
         progress("cpu baseline done")
