@@ -40,7 +40,7 @@ TOL_PER_CHANNEL = 1e-6
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "818c5b04ff44b4f1", "bytes": 9.737e13,
+    "c4": {"sha": "a4411341dc575ba9", "bytes": 8.1760e+13,
            "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
 }
 
