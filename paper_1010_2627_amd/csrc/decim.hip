@@ -108,14 +108,24 @@ __device__ __forceinline__ void dd_acc(double &hi, double &lo, dd x, dd y) {
   lo = __builtin_fma(x.lo, y.hi, lo);
 }
 
+// A staged complex operand with the sum of its parts, for the three-product
+// (Gauss) form of a complex multiply-add:
+//   re += ar br - ai bi,   im += (ar + ai)(br + bi) - ar br - ai bi
+// i.e. three double-double products per complex term instead of four; the
+// sums are formed once per staged element, exactly in double-double.
+struct Z3 {
+  dd re, im, s;
+};
+__device__ __forceinline__ Z3 z3(Z v) { return {v.re, v.im, r_add(v.re, v.im)}; }
+
 // C_e = cI I + (+/-) A_e B_e + [D_e], all [M][M], double-double C and D,
 // A and B double-double or FP64.  Grid: (tiles of C, energies).
 template <class TA, class TB>
 __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB *B, const Z *Dm, Z *C,
                                                            int64_t stride_bytes, int M, double cI,
                                                            int negate, const DecState *st, int check_done) {
-  __shared__ Z As[GT][GK + 1];
-  __shared__ Z Bs[GK][GT + 1];
+  __shared__ Z3 As[GT][GK + 1];
+  __shared__ Z3 Bs[GK][GT + 1];
   const int e = blockIdx.y;
   if (check_done && st[e].done) return;
   const int64_t eo = (int64_t)e * stride_bytes;
@@ -126,29 +136,30 @@ __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB
   const int tiles_n = (M + GT - 1) / GT;
   const int r0 = (blockIdx.x / tiles_n) * GT, c0 = (blockIdx.x % tiles_n) * GT;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[2][2][4];   // [i][j][re.hi, re.lo, im.hi, im.lo]
+  const Z zero = {{0.0, 0.0}, {0.0, 0.0}};
+  double acc[2][2][6];   // [i][j][p1.hi, p1.lo, p2.hi, p2.lo, p3.hi, p3.lo]
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][j][q] = 0.0;
+      for (int q = 0; q < 6; ++q) acc[i][j][q] = 0.0;
   for (int k0 = 0; k0 < M; k0 += GK) {
     // stage A[r0:r0+32, k0:k0+16] and B[k0:k0+16, c0:c0+32], zero outside M
     for (int i = tid; i < GT * GK; i += GTHREADS) {
       const int r = i / GK, k = i % GK;
       const int gr = r0 + r, gk = k0 + k;
-      As[r][k] = (gr < M && gk < M) ? zdd(Ae[(int64_t)gr * M + gk]) : Z{{0.0, 0.0}, {0.0, 0.0}};
+      As[r][k] = z3((gr < M && gk < M) ? zdd(Ae[(int64_t)gr * M + gk]) : zero);
     }
     for (int i = tid; i < GK * GT; i += GTHREADS) {
       const int k = i / GT, c = i % GT;
       const int gk = k0 + k, gc = c0 + c;
-      Bs[k][c] = (gk < M && gc < M) ? zdd(Be[(int64_t)gk * M + gc]) : Z{{0.0, 0.0}, {0.0, 0.0}};
+      Bs[k][c] = z3((gk < M && gc < M) ? zdd(Be[(int64_t)gk * M + gc]) : zero);
     }
     __syncthreads();
 #pragma unroll 2
     for (int k = 0; k < GK; ++k) {
-      Z a[2], b[2];
+      Z3 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[ty + 16 * i][k];
 #pragma unroll
@@ -157,11 +168,9 @@ __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const dd nai = {-a[i].im.hi, -a[i].im.lo};
           dd_acc(acc[i][j][0], acc[i][j][1], a[i].re, b[j].re);
-          dd_acc(acc[i][j][0], acc[i][j][1], nai, b[j].im);
-          dd_acc(acc[i][j][2], acc[i][j][3], a[i].re, b[j].im);
-          dd_acc(acc[i][j][2], acc[i][j][3], a[i].im, b[j].re);
+          dd_acc(acc[i][j][2], acc[i][j][3], a[i].im, b[j].im);
+          dd_acc(acc[i][j][4], acc[i][j][5], a[i].s, b[j].s);
         }
     }
     __syncthreads();
@@ -172,7 +181,10 @@ __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB
     for (int j = 0; j < 2; ++j) {
       const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
       if (r >= M || c >= M) continue;
-      Z v = {quick_two_sum(acc[i][j][0], acc[i][j][1]), quick_two_sum(acc[i][j][2], acc[i][j][3])};
+      const dd p1 = quick_two_sum(acc[i][j][0], acc[i][j][1]);
+      const dd p2 = quick_two_sum(acc[i][j][2], acc[i][j][3]);
+      const dd p3 = quick_two_sum(acc[i][j][4], acc[i][j][5]);
+      Z v = {r_sub(p1, p2), r_sub(r_sub(p3, p1), p2)};
       if (negate) v = c_neg(v);
       if (cI != 0.0 && r == c) v.re = r_add(v.re, dd{cI, 0.0});
       if (De) v = c_add(v, De[(int64_t)r * M + c]);
