@@ -47,6 +47,7 @@ SIGMAZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
 SEED_BASE = 10102627        # realization r uses SEED_BASE + r
 SEED_UNEVEN_LAYOUT = 10102626  # draws (W, L, w) of the uneven batch
 SEED_UNEVEN_STRIP = SEED_BASE + 1000  # strip p of the uneven batch uses this + p
+SEED_SYNTHETIC_SIGMA = 10102628     # synthetic boundary self-energies of the full-size sweep checks
 
 
 @dataclass
@@ -168,6 +169,22 @@ def onsite_disorder(strip: Strip, L: int, w: float, seed: int) -> np.ndarray:
 
 def clean_onsite(strip: Strip, L: int) -> np.ndarray:
     return np.zeros((L, strip.W, strip.norb, strip.norb), dtype=np.complex128)
+
+
+def synthetic_sigma(M: int, n: int, seed: int = SEED_SYNTHETIC_SIGMA, scale: float = 0.5) -> np.ndarray:
+    """n seeded matrices [n, M, M] of the form S = H - i G / 2 with H Hermitian and G
+    positive definite: valid retarded boundary terms for exercising the slice
+    recursion at sizes where the leads' own self-energies are costly to obtain on
+    a CPU (the recursion and the trace are defined for any such term)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((n, M, M), dtype=np.complex128)
+    for i in range(n):
+        A = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+        B = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+        H = scale * (A + A.conj().T) / (2.0 * np.sqrt(M))
+        G = scale * (B @ B.conj().T) / M + 0.05 * np.eye(M)
+        out[i] = H - 0.5j * G
+    return out
 
 
 def midpoint_grid(a: float, b: float, n: int) -> np.ndarray:
