@@ -166,6 +166,7 @@ def main():
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS (backward sweep) timing")
     ap.add_argument("--autotune", action="store_true",
                     help="time the sweep's launch shapes on a sample of the batch first and use the best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -249,6 +250,34 @@ def main():
     progress(f"fp64: {args.steps} timed step(s), {wall64:.2f} s/step (self-energies {ts64:.2f} s, "
              f"sweep {tw64:.2f} s, trace {tt64:.3f} s)")
     nopen = open_channels(b)
+    ldos_info = None
+    if not args.no_ldos:
+        # local density of states (backward sweep with checkpoints): the whole batch with every
+        # strip cut to its first 64 slices
+        host = b.probs.host.copy()
+        host["L"] = np.minimum(host["L"], 64)
+        sub = knit.ProblemTable.from_host(host)
+        wsl = torch.empty(max(knit.knit_ldos_workspace(b.dstrips, sub, "fp64", 0), 1), dtype=torch.uint8,
+                          device="cuda")
+        knit.knit_ldos(b.dstrips, sub, b.onsite, b.sigmaL, b.sigmaR, "fp64", workspace=wsl)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ld, lst = knit.knit_ldos(b.dstrips, sub, b.onsite, b.sigmaL, b.sigmaR, "fp64", workspace=wsl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tl = e0.elapsed_time(e1) / 1e3
+        steps_l = int(host["L"].sum())
+        Ms_l = np.array([b.strips[int(x)].M for x in host["strip"]], dtype=np.float64)
+        fl = float(np.sum(32.0 * Ms_l ** 3 * host["L"]))
+        ldos_info = {"slices_per_problem": "min(L, 64)", "seconds": round(tl, 4),
+                     "slice_steps_per_s": steps_l / tl,
+                     "tflops_at_32M3": fl / tl / 1e12,
+                     "frac_of_fp64_peak": fl / tl / 1e12 / PEAK_TFLOPS["fp64"],
+                     "flops_per_slice_step": "32*M^3 (forward inverse, checkpoint recompute, two products)",
+                     "problems_with_status": int((lst.cpu().numpy() != 0).sum()),
+                     "min_ldos": float(ld.min())}
+        del wsl, ld
+        progress(f"ldos: {tl:.2f} s for {steps_l} slice-steps")
 
     achieved = flops_per_pass / tw64 / 1e12
     tr = MEASURED_TRAFFIC.get(args.workload)
@@ -302,6 +331,8 @@ def main():
             "problems_with_status": badm,
         }
     out["n_open_range"] = [int(nopen.min()), int(nopen.max())]
+    if ldos_info is not None:
+        out["ldos"] = ldos_info
     if tuning is not None:
         out["autotune"] = tuning
     if not args.no_cpu_baseline:

@@ -191,6 +191,7 @@ size_t knit_ldos_workspace(const knit_strip *strips, int32_t n_strips,
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
   if (P == 0) return 0;
   const int st = resolve_stride(checkpoint_stride, Lmax);
+  if (sweep_mfma_supports(Mmax)) return ldos_mfma_workspace(Mmax, Lmax, st, precision, P);
   const int grid = P < 1024 ? P : 1024;
   return ldos_slab_bytes(Mmax, Lmax, st, precision) * (size_t)grid;
 }
@@ -210,9 +211,13 @@ int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *pr
   const size_t need = knit_ldos_workspace(strips, n_strips, probs_host, P, precision, checkpoint_stride);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
   StripTable tab = make_table(strips, n_strips);
-  hipError_t err = launch_ldos(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, st, ldos, pstatus,
-                               ws, ldos_slab_bytes(Mmax, Lmax, st, precision), Mmax,
-                               (hipStream_t)stream);
+  hipError_t err;
+  if (sweep_mfma_supports(Mmax))
+    err = launch_ldos_mfma(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, st, ldos, pstatus, ws, Mmax, Lmax,
+                           (hipStream_t)stream);
+  else
+    err = launch_ldos(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, st, ldos, pstatus, ws,
+                      ldos_slab_bytes(Mmax, Lmax, st, precision), Mmax, (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 

@@ -77,6 +77,10 @@ hipError_t launch_transmission(const StripTable &tab, const knit_problem *probs,
                                double *T_ward, hipStream_t stream);
 
 size_t ldos_slab_bytes(int Mmax, int Lmax, int stride, int precision);
+size_t ldos_mfma_workspace(int Mmax, int Lmax, int stride, int precision, int P);
+hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                            const knit_z *sigmaL, const knit_z *sigmaR, int precision, int stride, double *ldos,
+                            int32_t *pstatus, void *ws, int Mmax, int Lmax, hipStream_t stream);
 hipError_t launch_ldos(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
                        const knit_z *sigmaL, const knit_z *sigmaR, int precision, int stride,
                        double *ldos, int32_t *pstatus, void *ws, size_t slab_bytes, int Mmax,

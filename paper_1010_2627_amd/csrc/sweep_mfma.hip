@@ -372,7 +372,7 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
 // identity block), one norb x norb site block per thread.  gprev(r, c) and
 // G1prev(r, c) return g_{n-1} and G_{1,n-1} in natural order; with REFINE
 // A_n is also written in FP64 to A64.
-template <int no, class RG, bool REFINE, class GAcc, class G1Acc>
+template <int no, class RG, bool REFINE, bool BOTTOM, class GAcc, class G1Acc>
 __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, StripDev s, int Mp,
                                                         double E, const knit_z *D, const knit_z *sL,
                                                         const knit_z *sR, bool first, bool last, GAcc gprev,
@@ -440,7 +440,7 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
       }
     }
   }
-  if (first) return;
+  if (first || !BOTTOM) return;
   // bottom: row a, site block sb: -(G_{1,n-1} V^+)[a, sb]
   for (int blk = threadIdx.x; blk < Mp * Wp; blk += blockDim.x) {
     const int a = blk / Wp, sb = blk % Wp;
@@ -460,14 +460,14 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
   }
 }
 
-template <class RG, bool REFINE, class GAcc, class G1Acc>
+template <class RG, bool REFINE, bool BOTTOM = true, class GAcc, class G1Acc>
 __device__ void form_blocks(cpx<RG> *X, cpx<double> *A64, const StripDev &s, int Mp, double E,
                             const knit_z *D, const knit_z *sL, const knit_z *sR, bool first, bool last,
                             GAcc gprev, G1Acc G1prev) {
   switch (s.norb) {
-    case 1: form_blocks_n<1, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
-    case 2: form_blocks_n<2, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
-    default: form_blocks_n<4, RG, REFINE>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    case 1: form_blocks_n<1, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    case 2: form_blocks_n<2, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    default: form_blocks_n<4, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
   }
 }
 
@@ -489,6 +489,23 @@ __device__ void gather_vg(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int 
   }
 }
 
+// Y = Gm V^+ (columns of Gm gathered through vcol), padded columns zero
+template <class RS>
+__device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int Mp) {
+  const int M = s.M, no = s.norb;
+  const int64_t E2 = (int64_t)Mp * Mp;
+  for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) {
+    const int a = (int)(i / Mp), b = (int)(i % Mp);
+    cpx<double> acc = {0.0, 0.0};
+    if (a < M && b < M) {
+      const int sb = b / no, ob = b % no, cb = s.vcol[sb];
+      if (cb >= 0)
+        for (int j = 0; j < no; ++j)
+          acc = c_fma(cvt<double>(Gm[(int64_t)a * Mp + cb * no + j]), c_conj(vblk_at(s, sb, ob, j)), acc);
+    }
+    Y[i] = cvt<RS>(acc);
+  }
+}
 
 // Queue order for the persistent sweep.  policy 0: problem order.  policy 1:
 // longest processing time first, on the cost Mp^3 L binned at four bins per
@@ -738,9 +755,136 @@ inverse_fp64_kernel(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64
   if (fl && tid == 0) atomicOr(flags + (int64_t)e * flags_stride, fl);
 }
 
+// Local density of states on every slice (section 5.3-C sewing, the on-site
+// Green function of section 7.1-D) on the matrix cores, one workgroup per
+// problem from the same queue as the sweep:
+//   forward:  g_n = A_n^{-1} (elimination of A_n alone, unpermuted to natural
+//             order), g_{k st - 1} kept as checkpoint k;
+//   reverse:  per segment, g_n recomputed from its checkpoint, then
+//             G_LL = g_L,  G_nn = g_n + (g_n V^+) G_{n+1,n+1} (V g_n)
+//             with the two products on MFMA;  LDOS_n[i] = -Im (G_nn)_ii / pi.
+// Slab (Mp^2 elements each): X, Gnn, U, W, T, the segment's g [max(st, 2)],
+// checkpoints [ceil(Lmax / st)], then the elimination scratch.
+template <class RG, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z *onsite, const knit_z *sigmaL,
+                 const knit_z *sigmaR, int stride, double *ldos, int32_t *pstatus, char *ws, size_t slab_bytes,
+                 int Mpmax, int Lmax, unsigned int *queue, const int *order, int outer) {
+  using C = cpx<RG>;
+  __shared__ int next_p;
+  __shared__ int q[NT], pinv[NT];
+  __shared__ double sv[32];
+  __shared__ int si[64];
+  __shared__ C xchg[2 * 32];
+  __shared__ C prow[32];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t EE = (int64_t)Mpmax * Mpmax;
+  const int segbuf = stride < 2 ? 2 : stride;
+  const int nsegmax = (Lmax + stride - 1) / stride;
+  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  C *X = reinterpret_cast<C *>(slab);
+  C *Gnn = X + EE, *U = Gnn + EE, *W = U + EE, *T1 = W + EE;
+  C *seg = T1 + EE;                              // [segbuf][Mp][Mp]
+  C *cps = seg + (int64_t)segbuf * EE;           // [nsegmax][Mp][Mp]
+  C *Sb = cps + (int64_t)nsegmax * EE;           // [2 Mp][NO] scratch
+  C *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;      // [NO][Mp]   scratch
+  const double qnan = __builtin_nan("");
+  const double inv_pi = 0.318309886183790671537767526745;
+  for (;;) {
+    if (tid == 0) next_p = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int pi = next_p;
+    __syncthreads();
+    if (pi >= P) break;
+    const int p = order[pi];
+    const knit_problem pr = probs[p];
+    const StripDev s = tab.s[pr.strip];
+    const int M = s.M, no = s.norb, L = pr.L;
+    const int Mp = (M + MPAD - 1) / MPAD * MPAD;
+    const int64_t E2 = (int64_t)Mp * Mp;
+    const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
+    const int nseg = (L + stride - 1) / stride;
+    int flags = 0;
+    // g_n (natural order, into dst) from g_{n-1} (natural order, or none for n = 0)
+    auto step = [&](int n, const C *gprev, C *dst) {
+      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * M * no;
+      form_blocks<RG, false, false>(X, nullptr, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+                                    [=](int r, int c) { return cvt<double>(gprev[(int64_t)r * Mp + c]); },
+                                    [=](int r, int c) { return cpx<double>{0.0, 0.0}; });
+      __syncthreads();
+      flags |= outer == 128 ? gj_two_level<RG, NT, 128>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
+                            : gj_two_level<RG, NT, 64>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
+      for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
+      __syncthreads();
+      for (int64_t i = tid; i < E2; i += nt) {
+        const int a = (int)(i / Mp), b = (int)(i % Mp);
+        dst[i] = X[(int64_t)q[a] * Mp + pinv[b]];
+      }
+      __syncthreads();
+    };
+    // forward pass: checkpoint k holds g_{k st - 1} (k >= 1)
+    {
+      C *cur = seg, *prev = seg + E2;
+      for (int n = 0; n < L; ++n) {
+        step(n, prev, cur);
+        if ((n + 1) % stride == 0 && n + 1 < L) {
+          C *cp = cps + (int64_t)((n + 1) / stride) * E2;
+          for (int64_t i = tid; i < E2; i += nt) cp[i] = cur[i];
+          __syncthreads();
+        }
+        C *t = cur;
+        cur = prev;
+        prev = t;
+      }
+    }
+    // reverse pass, one segment at a time
+    double *out = ldos + pr.ldos_off;
+    for (int k = nseg - 1; k >= 0; --k) {
+      const int n0 = k * stride, n1 = min(L, n0 + stride);
+      for (int n = n0; n < n1; ++n) {
+        const C *gprev = n == n0 ? (k > 0 ? cps + (int64_t)k * E2 : seg) : seg + (int64_t)(n - n0 - 1) * E2;
+        step(n, gprev, seg + (int64_t)(n - n0) * E2);
+      }
+      for (int n = n1 - 1; n >= n0; --n) {
+        const C *g = seg + (int64_t)(n - n0) * E2;
+        if (n == L - 1) {
+          for (int64_t i = tid; i < E2; i += nt) Gnn[i] = g[i];
+        } else {
+          gather_gvdag<RG>(U, g, s, Mp);     // g V^+
+          gather_vg<RG>(W, g, s, Mp);        // V g
+          __syncthreads();
+          wg_gemm_mfma<RG>(Mp, Mp, Mp, U, Mp, Gnn, Mp, [&](int r, int c, RG &re, RG &im) {
+            T1[(int64_t)r * Mp + c] = C{re, im};
+          });
+          __syncthreads();
+          wg_gemm_mfma<RG>(Mp, Mp, Mp, T1, Mp, W, Mp, [&](int r, int c, RG &re, RG &im) {
+            const int64_t o = (int64_t)r * Mp + c;
+            Gnn[o] = C{g[o].re + re, g[o].im + im};
+          });
+        }
+        __syncthreads();
+        for (int i = tid; i < M; i += nt) out[(int64_t)n * M + i] = -(double)Gnn[(int64_t)i * Mp + i].im * inv_pi;
+        __syncthreads();
+      }
+    }
+    // non-finite check over the outputs
+    double bad = 0.0;
+    for (int64_t i = tid; i < (int64_t)L * M; i += nt) bad = fmax(bad, fabs(out[i]));
+    if (bad != bad) bad = INFINITY;
+    bad = wg_max_nan(bad, sv);
+    if (!(bad <= 1.79e308)) flags |= KNIT_P_NONFINITE;
+    if (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE))
+      for (int64_t i = tid; i < (int64_t)L * M; i += nt) out[i] = qnan;
+    if (tid == 0) pstatus[p] = flags;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
+
+static size_t order_bytes(int P) { return (((size_t)P * sizeof(int)) + 255) & ~size_t(255); }
 
 size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
   const size_t Mp = (size_t)mfma_padded(Mmax);
@@ -755,6 +899,51 @@ size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
 }
 
 bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= 512; }
+
+size_t ldos_mfma_slab_bytes(int Mmax, int Lmax, int stride, int precision) {
+  const size_t Mp = (size_t)mfma_padded(Mmax);
+  const size_t EE = Mp * Mp;
+  const size_t cs = precision == KNIT_FP64 ? 16 : 8;
+  const size_t segbuf = stride < 2 ? 2 : stride;
+  const size_t nseg = (Lmax + stride - 1) / stride;
+  size_t b = (5 + segbuf + nseg) * EE * cs + (2 * Mp * NO_MAX + NO_MAX * Mp) * cs;
+  return (b + 255) & ~size_t(255);
+}
+
+size_t ldos_mfma_workspace(int Mmax, int Lmax, int stride, int precision, int P) {
+  const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
+  return 256 + order_bytes(P) + ldos_mfma_slab_bytes(Mmax, Lmax, stride, precision) * (size_t)grid;
+}
+
+hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                            const knit_z *sigmaL, const knit_z *sigmaR, int precision, int stride, double *ldos,
+                            int32_t *pstatus, void *ws, int Mmax, int Lmax, hipStream_t stream) {
+  unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
+  int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
+  char *w = reinterpret_cast<char *>(ws) + 256 + order_bytes(P);
+  const int Mpmax = mfma_padded(Mmax);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  const knit_sweep_tuning tune = sweep_tuning_get(precision, Mpmax);
+  const size_t slab = ldos_mfma_slab_bytes(Mmax, Lmax, stride, precision);
+  int grid = tune.wg_per_cu * ncu;
+  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+  if (grid > P) grid = P;
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
+#define KNIT_LAUNCH(RG, NT)                                                                                   \
+  hipLaunchKernelGGL((ldos_mfma_kernel<RG, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, sigmaL, \
+                     sigmaR, stride, ldos, pstatus, w, slab, Mpmax, Lmax, queue, order, tune.outer)
+  if (precision == KNIT_FP64) {
+    if (tune.threads == 256) KNIT_LAUNCH(double, 256); else KNIT_LAUNCH(double, 512);
+  } else {
+    if (tune.threads == 256) KNIT_LAUNCH(float, 256); else KNIT_LAUNCH(float, 512);
+  }
+#undef KNIT_LAUNCH
+  return hipGetLastError();
+}
 
 size_t inverse_fp64_scratch_elems(int M) {
   const size_t Mp = (size_t)mfma_padded(M);
@@ -778,7 +967,6 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
 
 // Workspace: a 256-byte header (queue counter), the queue order [P] (padded to
 // 256 bytes), then one slab per workgroup.
-static size_t order_bytes(int P) { return (((size_t)P * sizeof(int)) + 255) & ~size_t(255); }
 
 // The refined sweep's second (FP64) pass shares the workspace.
 static size_t slab_for(int Mmax, int precision) {

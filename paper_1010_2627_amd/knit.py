@@ -287,8 +287,15 @@ def knit_transmission(strips, probs: ProblemTable, sigmaL, sigmaR, G1N, GN1=None
     return T, T_RL, T_w
 
 
+def knit_ldos_workspace(strips, probs: ProblemTable, precision="fp64", checkpoint_stride: int = 0) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tab = strip_table(strips)
+    return int(_lib.knit_ldos_workspace(tab, len(strips), _ptr(probs.host), probs.P, prec,
+                                        int(checkpoint_stride)))
+
+
 def knit_ldos(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, precision="fp64",
-              checkpoint_stride: int = 0, stream=None):
+              checkpoint_stride: int = 0, stream=None, workspace: torch.Tensor | None = None):
     """Returns (ldos flat float64 addressed by ldos_off, status [P])."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     tab = strip_table(strips)
@@ -301,10 +308,12 @@ def knit_ldos(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, precision="fp
     ldos = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
     status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
     wsz = _lib.knit_ldos_workspace(tab, len(strips), _ptr(probs.host), P, prec, int(checkpoint_stride))
-    ws = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
+    ws = workspace
+    if ws is None or ws.numel() < wsz:
+        ws = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
     code = _lib.knit_ldos(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
                           _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), prec, int(checkpoint_stride), _ptr(ldos),
-                          _ptr(status), _ptr(ws), int(wsz), _stream(stream))
+                          _ptr(status), _ptr(ws), int(ws.numel()), _stream(stream))
     _check(code, "knit_ldos")
     return ldos, status[:P]
 

@@ -143,3 +143,31 @@ def test_refine_guard_bounds_the_error_on_strong_disorder():
     nopen = np.maximum(1.0, np.ceil(np.abs(T64) - 1e-9))
     err = np.abs(Tm - T64) / nopen
     assert err[~fb].max(initial=0.0) <= 1e-4, (err.max(), int(fb.sum()))
+
+
+@gpu
+@pytest.mark.parametrize("case,prec", [("square70", "fp64"), ("rashba20", "fp64"), ("zigzag18", "fp64"),
+                                       ("square70", "fp32")])
+def test_ldos_on_matrix_cores_matches_oracle(case, prec):
+    """Backward (sewing) sweep on the matrix-core path: slices padded to 32 (M = 70, 40, 36),
+    spinful and zigzag couplings, checkpoint stride sqrt(L); FP64 at 1e-10, FP32 at 1e-3."""
+    from oracle import rgf as OR
+    from paper_1010_2627_amd import workload
+    if case == "square70":
+        b = workload.square_batch(70, 19, 2.0, 4, 1)
+    elif case == "rashba20":
+        b = workload.rashba_batch(20, 17, 2.0, 4, 1)
+    else:
+        b = workload.zigzag_batch(18, 15, 0.6, inputs.midpoint_grid(-2.9, 2.9, 4), 1)
+    st = b.strips[0]
+    E = b.energies[0]
+    sL, sR, _, _ = _oracle(b)
+    b.set_sigmas([sL], [sR])
+    ld, status = b.ldos(prec)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    ref = OR.ldos_rgf(st.H0, st.V_dense(), b.realizations[0].onsite, E, sL, sR)
+    tol = 1e-10 if prec == "fp64" else 1e-3
+    for ei in range(len(E)):
+        got = b.ldos_block(ld, ei).cpu().numpy()
+        assert np.max(np.abs(got - ref[ei]) / np.maximum(1, np.abs(ref[ei]))) < tol, (case, prec, ei)
