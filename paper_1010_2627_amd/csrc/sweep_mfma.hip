@@ -2,21 +2,27 @@
 //
 // Same recursion as the generic sweep (basic recursive Green function
 // algorithm, section 1): per slice the stacked matrix X = [A_n; -G_{1,n-1} V^+]
-// is reduced by Gauss-Jordan elimination with partial pivoting among the rows
-// of A_n, leaving g_n = A_n^{-1} on top and G_1n = G_{1,n-1} V^+ g_n below.
+// (2 Mp x Mp, Mp = M rounded up to 32, padded with an identity block) is
+// reduced by Gauss-Jordan elimination with partial pivoting among the rows of
+// A_n, leaving g_n = A_n^{-1} on top and G_1n = G_{1,n-1} V^+ g_n below.
 //
-// Blocked elimination with panels of NB columns (16 in FP64, 32 in FP32), one workgroup
-// (8 waves) per problem, persistent over the problems of the batch:
-//   1. panel: the candidate rows [k0, Mp) of the 32 panel columns sit in
-//      registers (one row per thread); 32 pivot steps, each a workgroup
-//      argmax on |re|+|im| (lowest row on ties), a row swap (registers for
-//      the panel, global memory for the other columns) and a rank-1 update
-//      of the panel, so the panel ends holding T = (A_PK)^{-1} on its pivot
-//      rows and the multipliers -A_rK T on the other candidate rows;
-//   2. multipliers of the remaining rows: X[r, K] <- -X[r, K] T   (MFMA)
-//   3. update: X[r, c] += X[r, K] X[P, c] for r outside P, c outside K (MFMA)
-//   4. pivot rows: X[P, c] <- T X[P, c]                              (MFMA)
-// Matrices are padded to Mp = 32 * ceil(M / 32) with an identity block.
+// One workgroup per problem, persistent over a queue of problems (atomic
+// counter over an order written by order_kernel, longest first by default).
+// The elimination is blocked in two levels (gj_two_level):
+//   * inner panels of 16 columns, factorised in registers (gj_panel): one
+//     logical row per thread, pivot = largest |re|+|im| found by wavefront
+//     reductions of a 32-bit key, rows never move in memory (a logical ->
+//     physical row map in LDS is permuted instead);
+//   * outer panels of 64 or 128 columns: the inner panels are applied to the
+//     outer panel's columns only, then one rank-NO update (multipliers, new
+//     pivot rows, and the update of everything else) touches the rest of the
+//     matrix once per outer panel;
+//   * every block product is a 32 x 32 (or 16 x 16) complex tile on MFMA
+//     (tile_gemm_window_flat: 4 real products per complex product, operands
+//     double-buffered in registers).
+// Two elimination buffers alternate between slices: slice n+1 assembles
+// A_{n+1} (form_blocks, one norb x norb site block per thread) directly from
+// slice n's result through its row and column permutations.
 //
 // Precision modes:
 //   FP64         elimination and state in FP64 (v_mfma_f64_16x16x4f64);
@@ -24,7 +30,12 @@
 //   FP32_REFINE  elimination in FP32; g_n and G_1n kept in FP64; per slice one
 //                refinement step on the inverse: R = I - A_n X0 with A_n and
 //                the product in FP64, then [g_n; G_1n] = [X0; G0] (I + R) with
-//                the correction product in FP32.
+//                the correction product in FP32.  A slice whose largest |R|
+//                exceeds the refine threshold hands its problem to a second,
+//                FP64 pass of the same call (KNIT_P_FALLBACK).
+//
+// The same machinery serves the batched FP64 inverse of the lead decimation
+// (inverse_fp64_kernel) and the LDOS backward sweep (ldos_mfma_kernel).
 
 #include <atomic>
 #include <mutex>
