@@ -65,6 +65,11 @@ WORKLOADS = {
                         "64 energies x 8 seeds = 512 problems"),
     "c1": dict(kind="square", W=16, L=64, w=1.0, n_energies=64, n_seeds=1,
                desc="square-lattice strip W=16, L=64, disorder U[-0.5,0.5], 64 energies"),
+    "c5": dict(kind="sampler", Nz=100, L=1024, w=0.6, n_test=4, n_train=128, train_L=(64, 128, 256),
+               train_w=(0.2, 0.8), steps=1500,
+               desc="learned energy sampling on a zigzag ribbon (slice dim 200, L=1024, disorder U[-0.3,0.3]): "
+                    "network trained by the library's BF16 kernels on 128 ribbons of the same width "
+                    "(L in {64,128,256}, w in [0.2,0.8]); 256 points vs 256 uniform, judged by 4096 points"),
     "c3": dict(kind="uneven", n_strips=512, n_energies=32,
                desc="uneven batch in one persistent launch: 512 square-lattice strips, W ~ U{32,64,..,256}, "
                     "L ~ U[256,2048], disorder U[-w/2,w/2] with w ~ U[0.5,3], 32 midpoint energies in "
@@ -101,6 +106,54 @@ def open_channels(b):
     for p, (ri, ei) in enumerate(c.prob_meta):
         per_class[(int(ri), int(ei))] = T[p]
     return np.array([per_class[(b.realizations[int(ri)].strip, int(ei))] for ri, ei in b.prob_meta])
+
+
+def sampler_bench(args, cfg):
+    """Learned energy sampling at the ribbon size of the learned-sampling workload: train, then
+    place 256 points per held-out ribbon and judge the integrated conductance against the
+    4096-point FP64 grid.  `value` is the transport throughput of the evaluation (T points/s)."""
+    import torch
+    from paper_1010_2627_amd import inputs, mlp, sampler as S
+    t0 = time.perf_counter()
+    X, Q, _ = S.generate_training_set(cfg["n_train"], Nz_choices=(cfg["Nz"],), L_choices=cfg["train_L"],
+                                      w_range=cfg["train_w"], chunk=16, progress=progress)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    progress(f"training set: {cfg['n_train']} curves in {t_data:.1f} s")
+    net = mlp.Network(S.SIZES, seed=1)
+    t1 = time.perf_counter()
+    hist = S.train(net, X, Q, steps=cfg["steps"], batch=256, lr=1e-3, log_every=250)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    H = float(np.mean(-(Q * np.log(np.maximum(Q, 1e-30))).sum(axis=1)))
+    progress(f"trained: KL {hist[0][1] - H:.4f} -> {hist[-1][1] - H:.4f} in {t_train:.1f} s")
+    test = [S.Ribbon(cfg["Nz"], cfg["L"], cfg["w"], inputs.SEED_BASE + r) for r in range(cfg["n_test"])]
+    t2 = time.perf_counter()
+    rows = S.evaluate(net, test, progress=progress)
+    torch.cuda.synchronize()
+    t_eval = time.perf_counter() - t2
+    n_points = cfg["n_test"] * (S.N_PROBE + S.N_TOTAL + S.N_JUDGE + 2 + 2 * S.N_LEARNED)
+    eu = np.array([r["err_uniform"] for r in rows])
+    el = np.array([r["err_learned"] for r in rows])
+    et = np.array([r["err_threshold"] for r in rows])
+    M = 2 * cfg["Nz"]
+    out = {
+        "metric": METRIC, "value": n_points / t_eval, "unit": "T(E) points/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": t_eval * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (transport), bf16/f32 (network)", "data": "synthetic",
+        "config": {"workload": args.workload, "description": cfg["desc"], "slice_dim_M": M,
+                   "test_ribbons": cfg["n_test"], "points_per_ribbon": n_points // cfg["n_test"]},
+        "sampler": {"integrated_conductance_rel_error": {
+                        "uniform_256": float(eu.mean()), "learned_256": float(el.mean()),
+                        "threshold_aware_256": float(et.mean())},
+                    "gain_learned_over_uniform": float(eu.mean() / el.mean()),
+                    "wins": f"{int((el < eu).sum())}/{len(el)}",
+                    "fallbacks": int(sum(r["fallback"] for r in rows)),
+                    "kl_start_end": [hist[0][1] - H, hist[-1][1] - H],
+                    "train_data_s": round(t_data, 2), "train_s": round(t_train, 2),
+                    "eval_s": round(t_eval, 2)},
+    }
+    print(json.dumps(out))
 
 
 def cpu_baseline(cfg, b, budget_s=20.0):
@@ -182,6 +235,9 @@ def main():
 
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if cfg["kind"] == "sampler":
+        sampler_bench(args, cfg)
+        return
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda")

@@ -75,9 +75,10 @@ def train_ribbons(n, Nz_choices=(6, 8, 10, 12, 14, 16), L_choices=(32, 64), w_ra
     return out
 
 
-def transmission_curves(ribbons, energies_list, chunk=64, device="cuda"):
+def transmission_curves(ribbons, energies_list, chunk=64, device="cuda", progress=None):
     """T(E) on the GPU path for every ribbon at its own energies (list of arrays).
-    Ribbons are grouped by cross-section so each strip class shares its self-energies."""
+    Ribbons are grouped by cross-section so each strip class shares its self-energies.
+    progress(msg), if given, is called after every chunk."""
     out = [None] * len(ribbons)
     for c0 in range(0, len(ribbons), chunk):
         idx = list(range(c0, min(len(ribbons), c0 + chunk)))
@@ -104,6 +105,8 @@ def transmission_curves(ribbons, energies_list, chunk=64, device="cuda"):
             rows = np.nonzero(b.prob_meta[:, 0] == ri)[0]
             out[i] = T[rows][sel]
         del b, G1N
+        if progress:
+            progress(f"transport: {idx[-1] + 1}/{len(ribbons)} ribbons")
     return out
 
 
@@ -195,11 +198,12 @@ def learned_points(net, ribbons, T_probe, nopen_dense, device="cuda"):
     return pts, fell_back
 
 
-def generate_training_set(n_curves, device="cuda", **kw):
+def generate_training_set(n_curves, device="cuda", progress=None, chunk=64, **kw):
     """Features and target densities of n_curves seeded ribbons."""
     rib = train_ribbons(n_curves, **kw)
     Ep, Ed = midpoints(N_PROBE), midpoints(N_BINS)
-    curves = transmission_curves(rib, [np.concatenate([Ep, Ed])] * len(rib), device=device)
+    curves = transmission_curves(rib, [np.concatenate([Ep, Ed])] * len(rib), chunk=chunk, device=device,
+                                 progress=progress)
     nopen = open_channels([r.Nz for r in rib], Ed, device)
     T_probe = [c[:N_PROBE] for c in curves]
     T_dense = [c[N_PROBE:] for c in curves]
@@ -223,19 +227,20 @@ def train(net, X, Q, steps=300, batch=256, lr=2e-3, wd=1e-4, seed=0, device="cud
     return hist
 
 
-def evaluate(net, ribbons, device="cuda"):
+def evaluate(net, ribbons, device="cuda", progress=None):
     """Integrated-conductance error of the learned 256 points and of 256 uniform points
     against the 4096-point judge, per ribbon."""
     Ep, Eu, Ej = midpoints(N_PROBE), midpoints(N_TOTAL), midpoints(N_JUDGE)
     ends = np.array([EMIN, EMAX])
     nopen = open_channels([r.Nz for r in ribbons], midpoints(N_BINS), device)
-    base = transmission_curves(ribbons, [np.concatenate([Ep, Eu, Ej, ends])] * len(ribbons), device=device)
+    base = transmission_curves(ribbons, [np.concatenate([Ep, Eu, Ej, ends])] * len(ribbons), chunk=1,
+                               device=device, progress=progress)
     n1, n2, n3 = N_PROBE, N_PROBE + N_TOTAL, N_PROBE + N_TOTAL + N_JUDGE
     T_probe = [c[:n1] for c in base]
     pts, fb = learned_points(net, ribbons, T_probe, nopen, device)
-    learned_T = transmission_curves(ribbons, pts, chunk=1, device=device)
+    learned_T = transmission_curves(ribbons, pts, chunk=1, device=device, progress=progress)
     thr_pts = [place(threshold_density(nopen[r.Nz])) for r in ribbons]
-    thr_T = transmission_curves(ribbons, thr_pts, chunk=1, device=device)
+    thr_T = transmission_curves(ribbons, thr_pts, chunk=1, device=device, progress=progress)
     rows = []
     for i in range(len(ribbons)):
         c = base[i]
