@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define KNIT_ABI_VERSION 1
+#define KNIT_ABI_VERSION 2
 #define KNIT_MAX_STRIPS 64     /* strip classes per batch */
 #define KNIT_MAX_M 1024        /* largest slice dimension */
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
@@ -269,6 +269,57 @@ int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *pr
               const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision,
               int32_t checkpoint_stride, double *ldos, int32_t *pstatus, void *ws,
               size_t ws_bytes, void *stream);
+
+/*
+ * Broadening factors (section 2.3: Gamma = i (Sigma - Sigma^+) is Hermitian
+ * positive semidefinite; its rank is the lead's number of open channels).
+ * For each of the n matrices sigma[e] ([M][M], row-major, consecutive) writes
+ * C[e] ([M][M], row-major) and rank[e] with Gamma_e = C_e C_e^+ + D_e, by a
+ * Cholesky factorisation with diagonal pivoting: columns are added while the
+ * largest remaining diagonal entry exceeds tol * s_e, s_e = max_i |(Sigma_e)_ii|
+ * (the scale of Gamma's rounding noise; tol <= 0 picks 1e-10, above the
+ * decimation's own error, so a lead's rank is its open channels and a Gamma
+ * of noise alone, outside the band, has rank 0).  The dropped part D_e is
+ * positive semidefinite with trace at most (M - rank[e]) * tol * s_e.  Columns >= rank[e] of C_e
+ * are zero and column k < rank[e] has a positive real entry at its pivot row,
+ * so rank[e] is also one plus the index of C_e's last nonzero column.  A
+ * non-finite Sigma gives rank[e] = -1 and a C_e of NaN.
+ *
+ *   M        1 <= M <= KNIT_MAX_M
+ *   sigma    device [n][M][M] input
+ *   C        device [n][M][M] output (may be addressed like sigma by sigma_off)
+ *   rank     device [n] output
+ * Asynchronous on stream; allocates nothing.
+ */
+int knit_gamma_factor(int32_t M, const knit_z *sigma, int32_t n, double tol, knit_z *C, int32_t *rank,
+                      void *stream);
+
+/*
+ * Projected sweep: the recursion of knit_rgf_sweep carrying
+ *   P_1 = C_L^+ g_1,   P_n = P_{n-1} V^+ g_n   (= C_L^+ G_1n)
+ * instead of G_1n, where Gamma_L = C_L C_L^+ (section 2.3; C_L as written by
+ * knit_gamma_factor for the left self-energy, addressed by sigma_off).  Only
+ * the r = C_L's columns up to its last nonzero one enter, so each slice's
+ * stacked elimination has Mp + r rows instead of 2 Mp (Mp = M rounded up to
+ * 32).  Writes P_L to G1Np ([M][M] at out_off, rows >= r zero) and, if GNN is
+ * not NULL, G_LL = g_L.  FP64 only; strips with M > 512 return
+ * KNIT_E_UNSUPPORTED.  The workspace is knit_rgf_sweep_workspace(..., KNIT_FP64,
+ * 0) bytes; other arguments as for knit_rgf_sweep.
+ */
+int knit_rgf_sweep_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                             const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
+                             knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Fisher-Lee transmission from the projected propagator (section 2.3, T_kl):
+ *   T[p] = || P_L C_R ||_F^2 = Re Tr[Gamma_L G_1L Gamma_R G_1L^+]
+ * with P_L from knit_rgf_sweep_projected (G1Np, at out_off) and Gamma_R =
+ * C_R C_R^+ (CR addressed by sigma_off).  FP64; T is device [P].
+ */
+int knit_transmission_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                const knit_problem *probs_dev, int32_t P, const knit_z *CR,
+                                const knit_z *G1Np, double *T, void *stream);
 
 #ifdef __cplusplus
 }

@@ -221,4 +221,44 @@ int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *pr
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 
+int knit_gamma_factor(int32_t M, const knit_z *sigma, int32_t n, double tol, knit_z *C, int32_t *rank,
+                      void *stream) {
+  if (M < 1 || M > KNIT_MAX_M || n < 0 || isnan(tol)) return KNIT_E_ARG;
+  if (n == 0) return KNIT_OK;
+  if (!sigma || !C || !rank) return KNIT_E_ARG;
+  if (!(tol > 0.0)) tol = 1e-10;
+  hipError_t err = launch_gamma_factor(M, sigma, n, tol, C, rank, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+int knit_rgf_sweep_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                             const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
+                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
+                             knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !onsite || !sigmaL || !sigmaR || !CL || !G1Np || !pstatus) return KNIT_E_ARG;
+  if (!sweep_mfma_supports(Mmax)) return KNIT_E_UNSUPPORTED;
+  const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, KNIT_FP64, 0);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_sweep_projected(tab, probs_dev, P, onsite, sigmaL, sigmaR, CL, G1Np, GNN, pstatus, ws,
+                                          Mmax, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+int knit_transmission_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                const knit_problem *probs_dev, int32_t P, const knit_z *CR,
+                                const knit_z *G1Np, double *T, void *stream) {
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, nullptr, nullptr)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !CR || !G1Np || !T) return KNIT_E_ARG;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_transmission_proj(tab, probs_dev, P, CR, G1Np, T, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
 }  // extern "C"

@@ -71,6 +71,14 @@ hipError_t launch_sweep(const StripTable &tab, const knit_problem *probs, int P,
                         knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, size_t slab_bytes,
                         int Mmax, hipStream_t stream);
 
+hipError_t launch_sweep_projected(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                                  const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
+                                  knit_z *GNN, int32_t *pstatus, void *ws, int Mmax, hipStream_t stream);
+hipError_t launch_gamma_factor(int M, const knit_z *sigma, int n, double tol, knit_z *C, int32_t *rank,
+                               hipStream_t stream);
+hipError_t launch_transmission_proj(const StripTable &tab, const knit_problem *probs, int P, const knit_z *CR,
+                                    const knit_z *G1Np, double *T, hipStream_t stream);
+
 hipError_t launch_transmission(const StripTable &tab, const knit_problem *probs, int P,
                                const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *G1N,
                                const knit_z *GN1, const knit_z *GNN, double *T, double *T_RL,

@@ -111,6 +111,18 @@ __device__ __forceinline__ double wg_max_nan(double v, double *sv) {
   return nan ? __builtin_nan("") : r;
 }
 
+// Columns of a factor C ([M][M] row-major, row stride M) up to its last
+// column with a nonzero (or NaN) entry: the number of columns that take part
+// in C C^+.  Called by the whole workgroup.
+__device__ int factor_columns(const knit_z *C, int M, double *sv) {
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < (int64_t)M * M; i += blockDim.x) {
+    const cpx<double> c = ld_z(C + i);
+    if (c.re != 0.0 || c.im != 0.0) m = fmax(m, (double)(i % M + 1));
+  }
+  return (int)wg_max_nan(m, sv);
+}
+
 // Rows of X are addressed through a logical -> physical map: pivoting permutes
 // the map (kept in LDS), never the rows in memory.  Rows >= Mp (the stacked
 // propagator rows) are never permuted.
@@ -387,7 +399,7 @@ template <int no, class RG, bool REFINE, bool BOTTOM, class GAcc, class G1Acc>
 __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, StripDev s, int Mp,
                                                         double E, const knit_z *D, const knit_z *sL,
                                                         const knit_z *sR, bool first, bool last, GAcc gprev,
-                                                        G1Acc G1prev) {
+                                                        G1Acc G1prev, int nbot) {
   const int M = s.M, W = M / no, Wp = Mp / no;
   const int64_t E2 = (int64_t)Mp * Mp;
   // top: site blocks (sa, sb), one output row oa at a time
@@ -452,10 +464,12 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
     }
   }
   if (first || !BOTTOM) return;
-  // bottom: row a, site block sb: -(G_{1,n-1} V^+)[a, sb]
-  for (int blk = threadIdx.x; blk < Mp * Wp; blk += blockDim.x) {
+  // bottom: row a, site block sb: -(G_{1,n-1} V^+)[a, sb]; rows a >= nbot (up to
+  // the next multiple of MPAD) are zero
+  const int Mb = (nbot + MPAD - 1) / MPAD * MPAD;
+  for (int blk = threadIdx.x; blk < Mb * Wp; blk += blockDim.x) {
     const int a = blk / Wp, sb = blk % Wp;
-    const int cb = (sb < W && a < M) ? s.vcol[sb] : -1;
+    const int cb = (sb < W && a < nbot) ? s.vcol[sb] : -1;
     cpx<double> gr[no];
     if (cb >= 0)
 #pragma unroll
@@ -474,11 +488,12 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
 template <class RG, bool REFINE, bool BOTTOM = true, class GAcc, class G1Acc>
 __device__ void form_blocks(cpx<RG> *X, cpx<double> *A64, const StripDev &s, int Mp, double E,
                             const knit_z *D, const knit_z *sL, const knit_z *sR, bool first, bool last,
-                            GAcc gprev, G1Acc G1prev) {
+                            GAcc gprev, G1Acc G1prev, int nbot = -1) {
+  if (nbot < 0) nbot = s.M;
   switch (s.norb) {
-    case 1: form_blocks_n<1, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
-    case 2: form_blocks_n<2, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
-    default: form_blocks_n<4, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev); break;
+    case 1: form_blocks_n<1, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
+    case 2: form_blocks_n<2, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
+    default: form_blocks_n<4, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
   }
 }
 
@@ -522,9 +537,9 @@ __device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, i
 // longest processing time first, on the cost Mp^3 L binned at four bins per
 // octave (a counting sort, one workgroup; order within a bin is whatever the
 // atomics give, which does not change any result).  Also clears the queue.
-constexpr int LPT_BINS = 256;
+constexpr int LPT_BINS = 1024;   // 16 bins per doubling of the cost (4.4 % wide)
 __global__ void __launch_bounds__(1024) order_kernel(StripTable tab, const knit_problem *probs, int P, int policy,
-                                                     int *order, unsigned int *queue) {
+                                                     const int *rows, int *order, unsigned int *queue) {
   __shared__ unsigned int cnt[LPT_BINS];
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) *queue = 0u;
@@ -534,9 +549,12 @@ __global__ void __launch_bounds__(1024) order_kernel(StripTable tab, const knit_
   }
   auto bin_of = [&](int p) {
     const knit_problem pr = probs[p];
-    const double Mp = (double)((tab.s[pr.strip].M + MPAD - 1) / MPAD * MPAD);
-    const double cost = Mp * Mp * Mp * (double)(pr.L > 0 ? pr.L : 1);
-    int b = (int)(4.0 * log2(cost));
+    const int mp = (tab.s[pr.strip].M + MPAD - 1) / MPAD * MPAD;
+    const double Mp = (double)mp;
+    // rows of the stacked elimination: Mp + Mp, or Mp + the projected rows
+    const double R = Mp + (rows ? (double)((rows[p] + MPAD - 1) / MPAD * MPAD) : Mp);
+    const double cost = Mp * Mp * R * (double)(pr.L > 0 ? pr.L : 1);
+    int b = (int)(16.0 * log2(cost));
     return b < 0 ? 0 : (b >= LPT_BINS ? LPT_BINS - 1 : b);
   };
   for (int b = tid; b < LPT_BINS; b += nt) cnt[b] = 0u;
@@ -555,14 +573,27 @@ __global__ void __launch_bounds__(1024) order_kernel(StripTable tab, const knit_
   for (int p = tid; p < P; p += nt) order[atomicAdd(&cnt[bin_of(p)], 1u)] = p;
 }
 
-template <class RG, class RS, bool REFINE, int NT>
+// Rows of the projected propagator, per problem: the columns of its C_L up to
+// the last nonzero one.  One workgroup per problem.
+__global__ void __launch_bounds__(256) proj_rows_kernel(StripTable tab, const knit_problem *probs, int P,
+                                                        const knit_z *CL, int *rows) {
+  __shared__ double sv[4];
+  const int p = blockIdx.x;
+  if (p >= P) return;
+  const knit_problem pr = probs[p];
+  const int M = tab.s[pr.strip].M;
+  const int r = factor_columns(CL + pr.sigma_off, M, sv);
+  if (threadIdx.x == 0) rows[p] = r < M ? r : M;
+}
+
+template <class RG, class RS, bool REFINE, int NT, bool PROJ = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sweep_mfma_kernel(StripTable tab, const knit_problem *probs, int P,
                                                         const knit_z *onsite, const knit_z *sigmaL,
                                                         const knit_z *sigmaR, knit_z *G1N, knit_z *GN1,
                                                         knit_z *GNN, int32_t *pstatus, char *ws,
                                                         size_t slab_bytes, int Mpmax, unsigned int *queue,
                                                         const int *order, double refine_tol, const int32_t *redo,
-                                                        int outer) {
+                                                        int outer, const knit_z *CL, const int *rows) {
   __shared__ int next_p;
   __shared__ int qa[NT], qb[NT];        // row order of the current / previous elimination
   __shared__ int pa[NT], pb[NT];        // and its inverse (column order of the inverse)
@@ -605,6 +636,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
     const int Mp = (M + MPAD - 1) / MPAD * MPAD;
     const int64_t E2 = (int64_t)Mp * Mp;
     const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
+    // projected propagator: C_L^+ G_1n, rl rows (Gamma_L = C_L C_L^+, C_L with rl
+    // columns up to its last nonzero one)
+    const int rl = PROJ ? rows[p] : 0;
+    const int rlp = (rl + MPAD - 1) / MPAD * MPAD;
+    const int nbot = PROJ ? rl : M;
     int flags = 0;
     int *q = qa, *pinv = pa, *qp = qb, *pinvp = pb;
     cpx<RG> *X = Xa, *Xp = Xb;
@@ -617,16 +653,30 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
       } else {
         // previous result in Xp: logical row r at physical row qp[r], column c of the
         // inverse at column pinvp[c]; G_11 = g_1 is the top of slice 1's result
-        const bool top = n == 1;
+        // (projected: C_L^+ G_11 is already the bottom of slice 1's result)
+        const bool top = n == 1 && !PROJ;
         form_blocks<RG, false>(X, A64, s, Mp, pr.E, D, sL, sR, false, n == L - 1,
                                [=](int r, int c) { return cvt<double>(Xp[(int64_t)qp[r] * Mp + pinvp[c]]); },
                                [=](int r, int c) {
                                  return cvt<double>(top ? Xp[(int64_t)qp[r] * Mp + pinvp[c]]
                                                         : Xp[(int64_t)(Mp + r) * Mp + pinvp[c]]);
-                               });
+                               },
+                               nbot);
+      }
+      if (PROJ && n == 0) {
+        // bottom block of slice 1: -C_L^+ (rows >= rl zero)
+        for (int64_t i = tid; i < (int64_t)rlp * Mp; i += nt) {
+          const int a = (int)(i / Mp), b = (int)(i % Mp);
+          cpx<double> v = {0.0, 0.0};
+          if (a < rl && b < M) {
+            const cpx<double> c = ld_z(CL + pr.sigma_off + (int64_t)b * M + a);
+            v = {-c.re, c.im};
+          }
+          X[E2 + i] = cvt<RG>(v);
+        }
       }
       __syncthreads();
-      const int R = n > 0 ? 2 * Mp : Mp;
+      const int R = PROJ ? Mp + rlp : (n > 0 ? 2 * Mp : Mp);
       flags |= outer == 128 ? gj_two_level<RG, NT, 128>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd)
                             : gj_two_level<RG, NT, 64>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd);
       for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
@@ -675,7 +725,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
           else G1[i - E2] = cvt<RS>(v);
         }
         __syncthreads();
-        if (n == 0) {
+        if (n == 0 && !PROJ) {
           for (int64_t i = tid; i < E2; i += nt) G1[i] = g[i];
           __syncthreads();
         }
@@ -706,7 +756,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
       for (int64_t i = tid; i < mm; i += nt) {
         const int a = (int)(i / M), b = (int)(i % M);
         const int64_t o = (int64_t)a * Mp + b;
-        bad = fmax(bad, c_abs1(G1[o]));
+        if (a < nbot) bad = fmax(bad, c_abs1(G1[o]));
         if (GNN) bad = fmax(bad, c_abs1(g[o]));
         if (want_n1) bad = fmax(bad, c_abs1(N1a[o]));
       }
@@ -723,7 +773,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
       for (int64_t i = tid; i < mm; i += nt) {
         const int a = (int)(i / M), b = (int)(i % M);
         const int64_t o = (int64_t)a * Mp + b;
-        st_z(G1N + pr.out_off + i, kill ? nanz : cvt<double>(G1[o]));
+        st_z(G1N + pr.out_off + i, kill ? nanz : (a < nbot ? cvt<double>(G1[o]) : cpx<double>{0.0, 0.0}));
         if (GNN) st_z(GNN + pr.out_off + i, kill ? nanz : cvt<double>(g[o]));
         if (want_n1) st_z(GN1 + pr.out_off + i, kill ? nanz : cvt<double>(N1a[o]));
       }
@@ -943,7 +993,8 @@ hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, in
   int grid = tune.wg_per_cu * ncu;
   if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
   if (grid > P) grid = P;
-  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr, order,
+                     queue);
 #define KNIT_LAUNCH(RG, NT)                                                                                   \
   hipLaunchKernelGGL((ldos_mfma_kernel<RG, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, sigmaL, \
                      sigmaR, stride, ldos, pstatus, w, slab, Mpmax, Lmax, queue, order, tune.outer)
@@ -953,6 +1004,38 @@ hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, in
     if (tune.threads == 256) KNIT_LAUNCH(float, 256); else KNIT_LAUNCH(float, 512);
   }
 #undef KNIT_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_projected(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                                  const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
+                                  knit_z *GNN, int32_t *pstatus, void *ws, int Mmax, hipStream_t stream) {
+  unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
+  int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
+  int *rows = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256 + order_bytes(P));
+  char *w = reinterpret_cast<char *>(ws) + 256 + 2 * order_bytes(P);
+  const int Mpmax = mfma_padded(Mmax);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  const knit_sweep_tuning tune = sweep_tuning_get(KNIT_FP64, Mpmax);
+  const size_t slab = sweep_mfma_slab_bytes(Mmax, KNIT_FP64);
+  int grid = tune.wg_per_cu * ncu;
+  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+  if (grid > P) grid = P;
+  hipLaunchKernelGGL(proj_rows_kernel, dim3(P), dim3(256), 0, stream, tab, probs, P, CL, rows);
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)rows, order,
+                     queue);
+  if (tune.threads == 256)
+    hipLaunchKernelGGL((sweep_mfma_kernel<double, double, false, 256, true>), dim3(grid), dim3(256), 0, stream, tab,
+                       probs, P, onsite, sigmaL, sigmaR, G1Np, (knit_z *)nullptr, GNN, pstatus, w, slab, Mpmax, queue,
+                       order, 0.0, (const int32_t *)nullptr, tune.outer, CL, rows);
+  else
+    hipLaunchKernelGGL((sweep_mfma_kernel<double, double, false, 512, true>), dim3(grid), dim3(512), 0, stream, tab,
+                       probs, P, onsite, sigmaL, sigmaR, G1Np, (knit_z *)nullptr, GNN, pstatus, w, slab, Mpmax, queue,
+                       order, 0.0, (const int32_t *)nullptr, tune.outer, CL, rows);
   return hipGetLastError();
 }
 
@@ -976,8 +1059,8 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
   return hipGetLastError();
 }
 
-// Workspace: a 256-byte header (queue counter), the queue order [P] (padded to
-// 256 bytes), then one slab per workgroup.
+// Workspace: a 256-byte header (queue counter), the queue order [P] and the
+// projected rows [P] (each padded to 256 bytes), then one slab per workgroup.
 
 // The refined sweep's second (FP64) pass shares the workspace.
 static size_t slab_for(int Mmax, int precision) {
@@ -991,7 +1074,7 @@ static size_t slab_for(int Mmax, int precision) {
 
 size_t sweep_mfma_workspace(int Mmax, int precision, int P) {
   const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
-  return 256 + order_bytes(P) + slab_for(Mmax, precision) * (size_t)grid;
+  return 256 + 2 * order_bytes(P) + slab_for(Mmax, precision) * (size_t)grid;
 }
 
 namespace {
@@ -1055,7 +1138,7 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
                              hipStream_t stream) {
   unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
   int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
-  char *w = reinterpret_cast<char *>(ws) + 256 + order_bytes(P);
+  char *w = reinterpret_cast<char *>(ws) + 256 + 2 * order_bytes(P);
   const int Mpmax = mfma_padded(Mmax);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -1074,10 +1157,12 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
     int grid = tune.wg_per_cu * ncu;
     if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
     if (grid > P) grid = P;
-    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, order, queue);
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr, order,
+                     queue);
 #define KNIT_LAUNCH(RG, RS, RF, NT)                                                                          \
   hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, \
-                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order, rtol, redo, tune.outer)
+                     sigmaL, sigmaR, G1N, GN1, GNN, pstatus, w, slab, Mpmax, queue, order, rtol, redo, tune.outer,  \
+                     (const knit_z *)nullptr, (const int *)nullptr)
     if (prec == KNIT_FP64) {
       if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
     } else if (prec == KNIT_FP32) {

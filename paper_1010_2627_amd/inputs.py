@@ -171,18 +171,26 @@ def clean_onsite(strip: Strip, L: int) -> np.ndarray:
     return np.zeros((L, strip.W, strip.norb, strip.norb), dtype=np.complex128)
 
 
-def synthetic_sigma(M: int, n: int, seed: int = SEED_SYNTHETIC_SIGMA, scale: float = 0.5) -> np.ndarray:
+def synthetic_sigma(M: int, n: int, seed: int = SEED_SYNTHETIC_SIGMA, scale: float = 0.5,
+                    rank: int | None = None) -> np.ndarray:
     """n seeded matrices [n, M, M] of the form S = H - i G / 2 with H Hermitian and G
     positive definite: valid retarded boundary terms for exercising the slice
     recursion at sizes where the leads' own self-energies are costly to obtain on
-    a CPU (the recursion and the trace are defined for any such term)."""
+    a CPU (the recursion and the trace are defined for any such term).  With
+    ``rank`` = r, G = scale * B B^+ / r for a Gaussian B of M x r instead: positive
+    semidefinite of rank r, like a lead with r open channels."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = np.empty((n, M, M), dtype=np.complex128)
     for i in range(n):
         A = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
-        B = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+        if rank is None:
+            B = rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))
+            G = scale * (B @ B.conj().T) / M + 0.05 * np.eye(M)
+        else:
+            B = rng.normal(size=(M, rank)) + 1j * rng.normal(size=(M, rank))
+            G = scale * (B @ B.conj().T) / max(rank, 1)
+            G = 0.5 * (G + G.conj().T)
         H = scale * (A + A.conj().T) / (2.0 * np.sqrt(M))
-        G = scale * (B @ B.conj().T) / M + 0.05 * np.eye(M)
         out[i] = H - 0.5j * G
     return out
 

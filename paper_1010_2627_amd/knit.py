@@ -64,6 +64,13 @@ _lib.knit_ldos.restype = c_i32
 _lib.knit_ldos.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp,
                            c_vp, c_sz, c_vp]
 
+_lib.knit_gamma_factor.restype = c_i32
+_lib.knit_gamma_factor.argtypes = [c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp]
+_lib.knit_rgf_sweep_projected.restype = c_i32
+_lib.knit_rgf_sweep_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                          c_vp, c_vp, c_sz, c_vp]
+_lib.knit_transmission_projected.restype = c_i32
+_lib.knit_transmission_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]
 
 
 class KnitSweepTuning(ctypes.Structure):
@@ -84,7 +91,8 @@ _lib.knit_get_refine_threshold.argtypes = []
 EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
-            "knit_sweep_tuning_get"]
+            "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
+            "knit_transmission_projected"]
 
 
 class KnitError(RuntimeError):
@@ -316,6 +324,55 @@ def knit_ldos(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, precision="fp
                           _ptr(status), _ptr(ws), int(ws.numel()), _stream(stream))
     _check(code, "knit_ldos")
     return ldos, status[:P]
+
+
+def knit_gamma_factor(M: int, sigma: torch.Tensor, n: int, tol: float = 0.0, C: torch.Tensor | None = None,
+                      stream=None):
+    """Gamma = C C^+ factors of n consecutive [M, M] self-energies (complex128 device tensor
+    of n*M*M elements, any shape).  Returns (C shaped like sigma, rank [n] int32)."""
+    sigma = _z(sigma)
+    assert sigma.numel() == n * M * M
+    if C is None:
+        C = torch.empty_like(sigma)
+    assert _z(C).numel() == sigma.numel()
+    rank = torch.empty(max(n, 1), dtype=torch.int32, device=sigma.device)
+    code = _lib.knit_gamma_factor(int(M), _ptr(sigma), int(n), float(tol), _ptr(C), _ptr(rank), _stream(stream))
+    _check(code, "knit_gamma_factor")
+    return C, rank[:n]
+
+
+def knit_rgf_sweep_projected(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, CL, G1Np=None,
+                             GNN: torch.Tensor | bool = False, stream=None, workspace: torch.Tensor | None = None):
+    """Projected sweep (FP64): returns (G1Np, GNN|None, status) with P_L = C_L^+ G_1L at out_off."""
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    need = _out_elems(strips, probs)
+    if G1Np is None:
+        G1Np = torch.empty(need, dtype=torch.complex128, device=dev)
+    if GNN is True:
+        GNN = torch.empty(need, dtype=torch.complex128, device=dev)
+    GNN = GNN if isinstance(GNN, torch.Tensor) else None
+    status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    wsz = _lib.knit_rgf_sweep_workspace(tab, len(strips), _ptr(probs.host), P, KNIT_FP64, 0)
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_rgf_sweep_projected(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P,
+                                         _ptr(_z(onsite)), _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(_z(CL)),
+                                         _ptr(G1Np), _ptr(GNN), _ptr(status), _ptr(workspace),
+                                         workspace.numel(), _stream(stream))
+    _check(code, "knit_rgf_sweep_projected")
+    return G1Np, GNN, status[:P]
+
+
+def knit_transmission_projected(strips, probs: ProblemTable, CR, G1Np, stream=None):
+    """T = ||P_L C_R||_F^2 per problem, device float64 [P]."""
+    tab = strip_table(strips)
+    T = torch.empty(max(probs.P, 1), dtype=torch.float64, device=G1Np.device)
+    code = _lib.knit_transmission_projected(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), probs.P,
+                                            _ptr(_z(CR)), _ptr(_z(G1Np)), _ptr(T), _stream(stream))
+    _check(code, "knit_transmission_projected")
+    return T[:probs.P]
 
 
 def _strip_M(s) -> int:

@@ -38,6 +38,10 @@ class Batch:
     sigmaR: torch.Tensor | None = None
     sigma_status: torch.Tensor | None = None
     sigma_iters: torch.Tensor | None = None
+    CL: torch.Tensor | None = None            # Gamma_L = C_L C_L^+ factors, addressed like sigmaL
+    CR: torch.Tensor | None = None
+    rankL: torch.Tensor | None = None         # per (strip class, energy) slot, in slot order
+    rankR: torch.Tensor | None = None
     prob_meta: np.ndarray | None = None      # [P, 2]: (realization, energy index)
 
     def __post_init__(self):
@@ -104,6 +108,30 @@ class Batch:
         self.sigma_status = torch.cat(stats) if stats else None
         self.sigma_iters = torch.cat(its) if its else None
         return self.sigmaL, self.sigmaR
+
+    def compute_gamma_factors(self, tol=0.0, stream=None):
+        """Factor Gamma = C C^+ of both leads at every (strip class, energy) slot."""
+        self.CL = torch.zeros(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        self.CR = torch.zeros(self.sigma_elems, dtype=torch.complex128, device=self.device)
+        rl, rr = [], []
+        for si, (ds, E) in enumerate(zip(self.dstrips, self.energies)):
+            if len(E) == 0:
+                continue
+            base, n = self.sigma_base[si], len(E) * ds.M * ds.M
+            rl.append(K.knit_gamma_factor(ds.M, self.sigmaL[base:base + n], len(E), tol, self.CL[base:base + n],
+                                          stream)[1])
+            rr.append(K.knit_gamma_factor(ds.M, self.sigmaR[base:base + n], len(E), tol, self.CR[base:base + n],
+                                          stream)[1])
+        self.rankL = torch.cat(rl) if rl else None
+        self.rankR = torch.cat(rr) if rr else None
+        return self.CL, self.CR
+
+    def sweep_projected(self, gnn=False, stream=None, workspace=None):
+        return K.knit_rgf_sweep_projected(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR,
+                                          self.CL, GNN=gnn, stream=stream, workspace=workspace)
+
+    def transmission_projected(self, G1Np, stream=None):
+        return K.knit_transmission_projected(self.dstrips, self.probs, self.CR, G1Np, stream)
 
     def set_sigmas(self, sigL_list, sigR_list):
         """Install externally computed self-energies: one [nE, M, M] array per strip class."""

@@ -53,7 +53,7 @@ def test_library_exports_every_sampler_kernel_entry(K):
 
 
 def test_abi_version_and_status_strings(K):
-    assert K.abi_version() == 1
+    assert K.abi_version() == 2
     assert K.status_string(K.KNIT_E_ARG) == "invalid argument"
     assert "singular" in K.status_string(K.KNIT_P_SINGULAR)
 
@@ -245,3 +245,36 @@ def test_sampler_kernel_argument_checks(K):
     assert lib.knit_mlp_adamw(4, FAKE, None, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.99, 1e-8, 0.0, 1, None) == K.KNIT_E_ARG
     assert lib.knit_mlp_adamw(4, FAKE, None, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.99, 1e-8, 0.0, 0, None) == K.KNIT_E_ARG
     assert lib.knit_mlp_adamw(4, FAKE, None, None, FAKE, FAKE, 1e-3, 0.9, 0.99, 1e-8, 0.0, 1, None) == K.KNIT_E_ARG
+
+
+def test_projected_path_argument_checks(K):
+    lib = K._lib
+    # Gamma factors
+    assert lib.knit_gamma_factor(0, FAKE, 2, 0.0, FAKE, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_gamma_factor(4096, FAKE, 2, 0.0, FAKE, FAKE, None) == K.KNIT_E_ARG    # above KNIT_MAX_M
+    assert lib.knit_gamma_factor(8, FAKE, -1, 0.0, FAKE, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_gamma_factor(8, FAKE, 2, float("nan"), FAKE, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_gamma_factor(8, None, 2, 0.0, FAKE, FAKE, None) == K.KNIT_E_ARG
+    assert lib.knit_gamma_factor(8, FAKE, 2, 0.0, FAKE, None, None) == K.KNIT_E_ARG
+    assert lib.knit_gamma_factor(8, None, 0, 0.0, None, None, None) == K.KNIT_OK
+    # projected sweep: FP64 matrix-core path only, the FP64 sweep's workspace
+    s = (K.KnitStrip * 1)(_strip(M=16))
+    probs = _probs([(0, 8, 0.1, 0, 0, 0, 0), (0, 8, 0.2, 0, 0, 256, 0)])
+    need = lib.knit_rgf_sweep_workspace(s, 1, probs.ctypes.data, 2, 0, 0)
+    sw = lambda **kw: lib.knit_rgf_sweep_projected(
+        s, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, kw.get("CL", FAKE), kw.get("G1Np", FAKE), None,
+        FAKE, kw.get("ws", FAKE), kw.get("wsb", need), None)
+    assert sw(CL=None) == K.KNIT_E_ARG
+    assert sw(G1Np=None) == K.KNIT_E_ARG
+    assert sw(wsb=need - 1) == K.KNIT_E_WORKSPACE
+    assert sw(ws=None) == K.KNIT_E_WORKSPACE
+    wide = (K.KnitStrip * 1)(_strip(M=544))
+    assert lib.knit_rgf_sweep_projected(wide, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                        FAKE, FAKE, 1 << 40, None) == K.KNIT_E_UNSUPPORTED
+    assert lib.knit_rgf_sweep_projected(s, 1, None, None, 0, None, None, None, None, None, None, None, None, 0,
+                                        None) == K.KNIT_OK
+    # projected transmission
+    tp = lib.knit_transmission_projected
+    assert tp(s, 1, probs.ctypes.data, FAKE, 2, None, FAKE, FAKE, None) == K.KNIT_E_ARG
+    assert tp(s, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, None, None) == K.KNIT_E_ARG
+    assert tp(s, 1, _probs([(0, 0, 0.1, 0, 0, 0, 0)]).ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, None) == K.KNIT_E_ARG
