@@ -3,16 +3,19 @@
 One step = the whole T(E) path over the batch, with the inputs resident in HBM:
   * the lead self-energies of both leads for every energy (double-double
     decimation);
-  * the slice sweep of every (energy, realization) problem;
-  * the Fisher-Lee trace.
+  * the broadening factors Gamma = C C^+ of both leads (pivoted Cholesky; the
+    rank is the lead's open channels);
+  * the slice sweep of every (energy, realization) problem, carrying the
+    projected propagator C_L^+ G_1n;
+  * the Fisher-Lee trace T = ||C_L^+ G_1L C_R||^2.
 
-Both precisions are timed over a full step:
-  * the FP64 matrix-core sweep;
+Beside the headline, full steps of two other paths are timed:
+  * the FP64 sweep carrying the whole G_1n (and the full trace);
   * the FP32 matrix-core sweep with one FP64-residual refinement per slice
-    inverse.
-Every mixed-precision T(E) is compared with the FP64 one, per open channel.
-The headline `value` is the step throughput of the path whose T(E) meets the
-tolerance on every point. The other path's figures sit beside it.
+    inverse (whole G_1n).
+Their T(E) is compared with the headline's, per open channel.  The headline
+`value` is the step throughput of the projected FP64 path, which meets the
+tolerance at every point; the others' figures sit beside it.
 
 Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -249,7 +252,7 @@ def main():
     Ms = np.array([b.strips[int(s)].M for s in b.probs.host["strip"]], dtype=np.float64)
     M = int(Ms.max())
     steps_per_pass = b.slice_steps()
-    flops_per_pass = float(np.sum(16.0 * Ms ** 3 * b.probs.host["L"]))
+    flops_full = float(np.sum(16.0 * Ms ** 3 * b.probs.host["L"]))
     G1N = torch.empty(int(np.sum(Ms ** 2)), dtype=torch.complex128, device="cuda")
     stream = torch.cuda.current_stream()
     wss = {}
@@ -274,12 +277,29 @@ def main():
             events.append(e)
         return T, status
 
+    G1Np = torch.empty_like(G1N)
+
+    def one_step_projected(events=None):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        b.compute_sigmas()
+        b.compute_gamma_factors()
+        e[1].record(stream)
+        _, _, status = knit.knit_rgf_sweep_projected(b.dstrips, b.probs, b.onsite, b.sigmaL, b.sigmaR, b.CL,
+                                                     G1Np=G1Np, workspace=ws_for("fp64"))
+        e[2].record(stream)
+        T = b.transmission_projected(G1Np)
+        e[3].record(stream)
+        if events is not None:
+            events.append(e)
+        return T, status
+
     def timed(prec, steps):
         evs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            T, status = one_step(prec, evs)
+            T, status = one_step_projected(evs) if prec == "projected" else one_step(prec, evs)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
@@ -299,19 +319,30 @@ def main():
                             "candidates_ms": [[c, round(t * 1e3, 2)] for c, t in r["results"]]}
             progress(f"autotune {prec}: {r['best']}")
     for i in range(args.warmup):
-        one_step("fp64")
+        one_step_projected()
         torch.cuda.synchronize()
         progress(f"warmup step {i + 1}/{args.warmup} done")
-    T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", args.steps)
-    progress(f"fp64: {args.steps} timed step(s), {wall64:.2f} s/step (self-energies {ts64:.2f} s, "
-             f"sweep {tw64:.2f} s, trace {tt64:.3f} s)")
+    Tp, wallp, (tsp, twp, ttp), badp = timed("projected", args.steps)
+    progress(f"fp64 projected: {args.steps} timed step(s), {wallp:.2f} s/step (self-energies and "
+             f"broadening factors {tsp:.2f} s, sweep {twp:.2f} s, trace {ttp:.3f} s)")
+    rankL, _ = b.problem_ranks()
+    # algorithmic flops of the projected sweep per slice: the slice inverse (8 M^3) and the
+    # product P_{n-1} V^+ g_n with r = rank(Gamma_L) rows (8 M^2 r)
+    flops_proj = float(np.sum((8.0 * Ms ** 3 + 8.0 * Ms ** 2 * rankL) * b.probs.host["L"]))
+    T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", 1)
+    progress(f"fp64 full propagator: {wall64:.2f} s/step (sweep {tw64:.2f} s)")
     nopen = open_channels(b)
+    dTp = np.abs(Tp - T64) / np.maximum(1, nopen)
     ldos_info = None
     if not args.no_ldos:
         # local density of states (backward sweep with checkpoints): the whole batch with every
         # strip cut to its first 64 slices
         host = b.probs.host.copy()
         host["L"] = np.minimum(host["L"], 64)
+        # LDOS blocks of the cut strips, packed: every value of the output is written
+        Ms_sub = np.array([b.strips[int(x)].M for x in host["strip"]], dtype=np.int64)
+        sizes = host["L"].astype(np.int64) * Ms_sub
+        host["ldos_off"] = np.concatenate([[0], np.cumsum(sizes)[:-1]])
         sub = knit.ProblemTable.from_host(host)
         wsl = torch.empty(max(knit.knit_ldos_workspace(b.dstrips, sub, "fp64", 0), 1), dtype=torch.uint8,
                           device="cuda")
@@ -331,21 +362,21 @@ def main():
                      "frac_of_fp64_peak": fl / tl / 1e12 / PEAK_TFLOPS["fp64"],
                      "flops_per_slice_step": "32*M^3 (forward inverse, checkpoint recompute, two products)",
                      "problems_with_status": int((lst.cpu().numpy() != 0).sum()),
-                     "min_ldos": float(ld.min())}
+                     "min_ldos": float(ld[:int(sizes.sum())].min())}
         del wsl, ld
         progress(f"ldos: {tl:.2f} s for {steps_l} slice-steps")
 
-    achieved = flops_per_pass / tw64 / 1e12
+    achieved = flops_proj / twp / 1e12
     tr = MEASURED_TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if tr and tr["sha"] == sweep_source_sha() else None
     out = {
         "metric": METRIC,
-        "value": steps_per_pass / wall64,
+        "value": steps_per_pass / wallp,
         "unit": "slice-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall64 * 1e3,
+        "ms_per_step": wallp * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -353,18 +384,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": cfg["desc"], "slice_dim_M_max": M,
                    "problems": b.P, "slice_steps_per_step": steps_per_pass,
-                   "headline_precision": "fp64 (the path meeting the T tolerance at every point)"},
-        "phases_s": {"lead_selfenergy_dd": round(float(ts64), 4), "sweep": round(float(tw64), 4),
-                     "trace": round(float(tt64), 4)},
-        "sweep_slice_steps_per_s": steps_per_pass / tw64,
-        "t_points_per_s": b.P / wall64,
-        "problems_with_status": bad64,
+                   "headline_precision": "fp64, projected propagator C_L^+ G_1n (meets the T tolerance "
+                                         "at every point)"},
+        "phases_s": {"lead_selfenergy_dd_and_gamma_factors": round(float(tsp), 4), "sweep": round(float(twp), 4),
+                     "trace": round(float(ttp), 4)},
+        "sweep_slice_steps_per_s": steps_per_pass / twp,
+        "t_points_per_s": b.P / wallp,
+        "problems_with_status": badp,
+        "gamma_rank_range": [int(rankL.min()), int(rankL.max())],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (calibrated counters)",
                      "traffic_source": tr["profile"] if traffic else None,
-                     "kernel": "sweep_mfma_kernel<double> (FP64 MFMA)",
-                     "flops_per_slice_step": "16*M^3 (8M^3 inverse + 8M^3 propagator)"},
+                     "kernel": "sweep_mfma_kernel<double, double, false, 512, true> (FP64 MFMA, projected)",
+                     "flops_per_slice_step": "8*M^3 + 8*M^2*r (inverse + projected propagator, r = rank "
+                                             "Gamma_L)",
+                     "flops_per_step": flops_proj},
+        "fp64_full_propagator": {
+            "slice_steps_per_s": steps_per_pass / wall64,
+            "sweep_s": round(float(tw64), 4),
+            "sweep_slice_steps_per_s": steps_per_pass / tw64,
+            "tflops_at_16M3": flops_full / tw64 / 1e12,
+            "frac_of_fp64_peak": flops_full / tw64 / 1e12 / PEAK_TFLOPS["fp64"],
+            "projected_sweep_speedup": tw64 / twp,
+            "max_dT_per_open_channel_projected_vs_full": float(dTp.max()),
+            "problems_with_status": bad64,
+        },
     }
     if not args.no_mixed:
         Tm, wallm, (tsm, twm, ttm), badm = timed("fp32_refine", 1)
@@ -372,13 +417,14 @@ def main():
         dT = np.abs(Tm - T64)
         rel = dT / np.maximum(1, nopen)
         ok = rel <= TOL_PER_CHANNEL
-        am = flops_per_pass / twm / 1e12
+        am = flops_full / twm / 1e12
         out["fp32_refine"] = {
             "slice_steps_per_s": steps_per_pass / wallm,
             "sweep_s": round(float(twm), 4),
             "sweep_slice_steps_per_s": steps_per_pass / twm,
             "frac_of_fp32_peak": am / PEAK_TFLOPS["fp32_refine"],
-            "sweep_speedup_vs_fp64": tw64 / twm,
+            "sweep_speedup_vs_fp64_full": tw64 / twm,
+            "sweep_speedup_vs_fp64_projected": twp / twm,
             "max_dT_per_open_channel_vs_fp64": float(rel.max()),
             "median_dT_per_open_channel_vs_fp64": float(np.median(rel)),
             "max_abs_dT_vs_fp64": float(dT.max()),

@@ -534,9 +534,11 @@ __device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, i
 }
 
 // Queue order for the persistent sweep.  policy 0: problem order.  policy 1:
-// longest processing time first, on the cost Mp^3 L binned at four bins per
-// octave (a counting sort, one workgroup; order within a bin is whatever the
-// atomics give, which does not change any result).  Also clears the queue.
+// longest processing time first, on the cost Mp^2 R L (R = rows of the stacked
+// elimination: 2 Mp, or Mp plus the projected rows when `rows` is given),
+// binned at 16 bins per doubling (a counting sort, one workgroup; order within
+// a bin is whatever the atomics give, which does not change any result).  Also
+// clears the queue.
 constexpr int LPT_BINS = 1024;   // 16 bins per doubling of the cost (4.4 % wide)
 __global__ void __launch_bounds__(1024) order_kernel(StripTable tab, const knit_problem *probs, int P, int policy,
                                                      const int *rows, int *order, unsigned int *queue) {

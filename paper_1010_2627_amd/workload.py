@@ -126,6 +126,13 @@ class Batch:
         self.rankR = torch.cat(rr) if rr else None
         return self.CL, self.CR
 
+    def problem_ranks(self) -> tuple[np.ndarray, np.ndarray]:
+        """(rank of Gamma_L, rank of Gamma_R) of every problem, from its (strip class, energy) slot."""
+        slot_base = np.cumsum([0] + [len(E) for E in self.energies])[:-1]
+        slot = np.array([slot_base[r.strip] + int(ei) for r, (ri, ei) in
+                         ((self.realizations[int(m[0])], m) for m in self.prob_meta)], dtype=np.int64)
+        return self.rankL.cpu().numpy()[slot], self.rankR.cpu().numpy()[slot]
+
     def sweep_projected(self, gnn=False, stream=None, workspace=None):
         return K.knit_rgf_sweep_projected(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR,
                                           self.CL, GNN=gnn, stream=stream, workspace=workspace)

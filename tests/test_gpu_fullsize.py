@@ -85,3 +85,36 @@ def test_full_size_spinful_batch_with_lead_self_energies_is_bounded_and_reproduc
     assert np.max(np.abs(nopen - np.rint(nopen))) < 1e-8
     T = T.cpu().numpy().reshape(len(b.realizations), -1)
     assert np.all(T >= -1e-9) and np.all(T <= np.rint(nopen)[None, :] + 1e-8)
+
+
+@gpu
+def test_full_size_spinful_ldos_matches_oracle_and_is_nonnegative():
+    """LDOS (backward sweep with checkpoints) on the spinful W=256 batch in the launch shape
+    the benchmark times (slice dim 512: 512 threads, 128-wide outer panels), strips cut to
+    their first 24 slices (checkpoint stride 5) with packed output blocks: two sampled
+    problems against the oracle's backward sweep at 1e-10, and -Im G_ii / pi >= 0 on every
+    site of every problem (the diagonal of the spectral function G Gamma G^+)."""
+    from oracle import rgf as OR
+    from paper_1010_2627_amd import knit
+    b = _batch("spinful_w256")
+    st = b.strips[0]
+    nE = len(b.energies[0])
+    sL = inputs.synthetic_sigma(st.M, nE)
+    sR = inputs.synthetic_sigma(st.M, nE, seed=inputs.SEED_SYNTHETIC_SIGMA + 1)
+    b.set_sigmas([sL], [sR])
+    host = b.probs.host.copy()
+    host["L"] = 24
+    host["ldos_off"] = np.arange(b.P, dtype=np.int64) * 24 * st.M
+    sub = knit.ProblemTable.from_host(host)
+    ld, status = knit.knit_ldos(b.dstrips, sub, b.onsite, b.sigmaL, b.sigmaR, "fp64", checkpoint_stride=5)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    ld = ld[:b.P * 24 * st.M].cpu().numpy().reshape(b.P, 24, st.M)
+    assert np.all(np.isfinite(ld)) and ld.min() >= -1e-12
+    V = st.V_dense()
+    for ri, ei in [(0, 5), (7, 60)]:
+        p = ri * nE + ei
+        assert tuple(b.prob_meta[p]) == (ri, ei)
+        E = np.array([b.energies[0][ei]])
+        ref = OR.ldos_rgf(st.H0, V, b.realizations[ri].onsite[:24], E, sL[ei:ei + 1], sR[ei:ei + 1])[0]
+        assert np.max(np.abs(ld[p] - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10, (ri, ei)
