@@ -146,7 +146,12 @@ const char *knit_status_string(int code);
  * (scale = max(1, max|H0|, max|V|)) or after max_iter steps (KNIT_P_NOCONV).
  * Each step's inverse (z - eps_k)^{-1} is an FP64 matrix-core inverse refined
  * by two double-double Newton steps; M above KNIT_MAX_SELFENERGY_M returns
- * KNIT_E_UNSUPPORTED.  The call queues max_iter steps without waiting for the
+ * KNIT_E_UNSUPPORTED.  Every result is checked against the lead's defining
+ * equation, max |(z - H0 - Sigma) g - I| <= 1e-12 in double-double; an energy
+ * that fails (near an eigenvalue of the single slice H0, where every doubling
+ * step is singular, e.g. E = 0 on a bipartite strip with a zero mode) is
+ * redone with a cell of two slices, for up to 4 energies per call and
+ * M <= 256; any other failing energy gets KNIT_P_NOCONV and a NaN Sigma.  The call queues max_iter steps without waiting for the
  * device; energies that have converged skip the remaining steps.
  *
  *   strip     host   strip class

@@ -37,6 +37,22 @@
 //   * convergence is decided on the device per energy: later launches skip
 //     finished energies, and the host issues max_iter iterations without
 //     waiting for the device.
+//
+// Energies at an eigenvalue of the single slice: every doubling step k
+// inverts z - eps_k, which is singular where E is an eigenvalue of a strip of
+// 2^(k+1) - 1 slices; at E = 0 on a bipartite strip with a zero mode (square
+// lattice, odd width) that holds for every k, and the 1/eta-sized parts of
+// the decimated couplings amplify rounding by about eta^-2, beyond double-
+// double.  Every result is therefore checked against its defining equation,
+//   R = (z - h - Sigma) g - I,   g the surface Green function,
+// in double-double, and an energy with max |R| > 1e-12 (or a non-finite
+// result) is redone with a cell of two slices,
+//   h2 = [[h, alpha], [beta, h]],  alpha2 = [[0, 0], [alpha, 0]],
+// whose strips all have an even number of slices: the surface slice's g is
+// the leading block of the cell's surface Green function (the trailing block
+// for the right lead's surface of a side-2 run).  Up to RETRY_SLOTS energies
+// per call are redone, when 2M fits the matrix-core inverse; any other failing
+// energy gets KNIT_P_NOCONV and NaN output.
 
 #include "knit_internal.h"
 
@@ -57,10 +73,23 @@ constexpr int EW_BLOCKS = 64;   // elementwise kernels: workgroups per energy
 
 // Per-energy state, at the start of the workspace.
 struct DecState {
-  int32_t done, iters, flags, pad;
+  int32_t done, iters, flags;
+  int32_t skip;              // 1: left alone by the final stage (an unused retry slot)
   unsigned long long amax;   // bits of a non-negative double (max |a|, |b| of the step)
   unsigned long long scale;  // bits of max(1, max |H0|, max |V|)
+  unsigned long long resid;  // bits of max |R| of the defining equation's check
 };
+
+constexpr int RETRY_SLOTS = 4;          // energies redone with the two-slice cell per call
+constexpr double RESID_TOL = 1e-12;     // max |(z - h - Sigma) g - I| accepted
+constexpr int DEC_RETRY = 1 << 8;       // internal flag bits (never reported)
+constexpr int DEC_FAILED = 1 << 9;
+constexpr int DEC_PUBLIC = KNIT_P_SINGULAR | KNIT_P_NOCONV | KNIT_P_NONFINITE;
+
+// Skip rules of the per-energy kernels: 0 none, 1 finished energies, 2 unused slots.
+__device__ __forceinline__ bool dec_skip(const DecState *st, int e, int check) {
+  return (check == 1 && st[e].done) || (check == 2 && st[e].skip);
+}
 
 // Per-energy slab: buffer offsets in bytes.
 struct Slab {
@@ -127,69 +156,72 @@ __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB
   __shared__ Z3 As[GT][GK + 1];
   __shared__ Z3 Bs[GK][GT + 1];
   const int e = blockIdx.y;
-  if (check_done && st[e].done) return;
+  if (dec_skip(st, e, check_done)) return;
   const int64_t eo = (int64_t)e * stride_bytes;
   const TA *Ae = reinterpret_cast<const TA *>(reinterpret_cast<const char *>(A) + eo);
   const TB *Be = reinterpret_cast<const TB *>(reinterpret_cast<const char *>(B) + eo);
   Z *Ce = reinterpret_cast<Z *>(reinterpret_cast<char *>(C) + eo);
   const Z *De = Dm ? reinterpret_cast<const Z *>(reinterpret_cast<const char *>(Dm) + eo) : nullptr;
   const int tiles_n = (M + GT - 1) / GT;
-  const int r0 = (blockIdx.x / tiles_n) * GT, c0 = (blockIdx.x % tiles_n) * GT;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const Z zero = {{0.0, 0.0}, {0.0, 0.0}};
-  double acc[2][2][6];   // [i][j][p1.hi, p1.lo, p2.hi, p2.lo, p3.hi, p3.lo]
+  // tiles of C, strided over the grid's x dimension
+  for (int tile = blockIdx.x; tile < tiles_n * tiles_n; tile += gridDim.x) {
+    const int r0 = (tile / tiles_n) * GT, c0 = (tile % tiles_n) * GT;
+    const Z zero = {{0.0, 0.0}, {0.0, 0.0}};
+    double acc[2][2][6];   // [i][j][p1.hi, p1.lo, p2.hi, p2.lo, p3.hi, p3.lo]
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 6; ++q) acc[i][j][q] = 0.0;
-  for (int k0 = 0; k0 < M; k0 += GK) {
-    // stage A[r0:r0+32, k0:k0+16] and B[k0:k0+16, c0:c0+32], zero outside M
-    for (int i = tid; i < GT * GK; i += GTHREADS) {
-      const int r = i / GK, k = i % GK;
-      const int gr = r0 + r, gk = k0 + k;
-      As[r][k] = z3((gr < M && gk < M) ? zdd(Ae[(int64_t)gr * M + gk]) : zero);
-    }
-    for (int i = tid; i < GK * GT; i += GTHREADS) {
-      const int k = i / GT, c = i % GT;
-      const int gk = k0 + k, gc = c0 + c;
-      Bs[k][c] = z3((gk < M && gc < M) ? zdd(Be[(int64_t)gk * M + gc]) : zero);
-    }
-    __syncthreads();
+        for (int q = 0; q < 6; ++q) acc[i][j][q] = 0.0;
+    for (int k0 = 0; k0 < M; k0 += GK) {
+      // stage A[r0:r0+32, k0:k0+16] and B[k0:k0+16, c0:c0+32], zero outside M
+      for (int i = tid; i < GT * GK; i += GTHREADS) {
+        const int r = i / GK, k = i % GK;
+        const int gr = r0 + r, gk = k0 + k;
+        As[r][k] = z3((gr < M && gk < M) ? zdd(Ae[(int64_t)gr * M + gk]) : zero);
+      }
+      for (int i = tid; i < GK * GT; i += GTHREADS) {
+        const int k = i / GT, c = i % GT;
+        const int gk = k0 + k, gc = c0 + c;
+        Bs[k][c] = z3((gk < M && gc < M) ? zdd(Be[(int64_t)gk * M + gc]) : zero);
+      }
+      __syncthreads();
 #pragma unroll 2
-    for (int k = 0; k < GK; ++k) {
-      Z3 a[2], b[2];
+      for (int k = 0; k < GK; ++k) {
+        Z3 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[ty + 16 * i][k];
+        for (int i = 0; i < 2; ++i) a[i] = As[ty + 16 * i][k];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[k][tx + 16 * j];
+        for (int j = 0; j < 2; ++j) b[j] = Bs[k][tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          dd_acc(acc[i][j][0], acc[i][j][1], a[i].re, b[j].re);
-          dd_acc(acc[i][j][2], acc[i][j][3], a[i].im, b[j].im);
-          dd_acc(acc[i][j][4], acc[i][j][5], a[i].s, b[j].s);
-        }
+          for (int j = 0; j < 2; ++j) {
+            dd_acc(acc[i][j][0], acc[i][j][1], a[i].re, b[j].re);
+            dd_acc(acc[i][j][2], acc[i][j][3], a[i].im, b[j].im);
+            dd_acc(acc[i][j][4], acc[i][j][5], a[i].s, b[j].s);
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+        if (r >= M || c >= M) continue;
+        const dd p1 = quick_two_sum(acc[i][j][0], acc[i][j][1]);
+        const dd p2 = quick_two_sum(acc[i][j][2], acc[i][j][3]);
+        const dd p3 = quick_two_sum(acc[i][j][4], acc[i][j][5]);
+        Z v = {r_sub(p1, p2), r_sub(r_sub(p3, p1), p2)};
+        if (negate) v = c_neg(v);
+        if (cI != 0.0 && r == c) v.re = r_add(v.re, dd{cI, 0.0});
+        if (De) v = c_add(v, De[(int64_t)r * M + c]);
+        Ce[(int64_t)r * M + c] = v;
+      }
   }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-      if (r >= M || c >= M) continue;
-      const dd p1 = quick_two_sum(acc[i][j][0], acc[i][j][1]);
-      const dd p2 = quick_two_sum(acc[i][j][2], acc[i][j][3]);
-      const dd p3 = quick_two_sum(acc[i][j][4], acc[i][j][5]);
-      Z v = {r_sub(p1, p2), r_sub(r_sub(p3, p1), p2)};
-      if (negate) v = c_neg(v);
-      if (cI != 0.0 && r == c) v.re = r_add(v.re, dd{cI, 0.0});
-      if (De) v = c_add(v, De[(int64_t)r * M + c]);
-      Ce[(int64_t)r * M + c] = v;
-    }
 }
 
 __device__ __forceinline__ char *slab_ptr(char *ws, const Slab &sl, int e, size_t off) {
@@ -227,18 +259,52 @@ __global__ void __launch_bounds__(EW) dec_init_kernel(StripDev s, int side, char
 
 __global__ void dec_reset_state_kernel(DecState *st, int nE) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nE) st[e] = DecState{0, 0, 0, 0, 0ull, 0ull};
+  if (e < nE) st[e] = DecState{0, 0, 0, 0, 0ull, 0ull, 0ull};
+}
+
+// Two-slice cell of a retry slot (dimension 2M):
+//   eps_s = eps_r = eps = [[h, alpha], [beta, h]],  a = [[0, 0], [alpha, 0]],
+//   b = a^+ = [[0, beta], [0, 0]],  Vf = diag(alpha, alpha),  Vb = diag(beta, beta)
+// (alpha = V, beta = V^+ for the left lead, swapped for side 1).
+__global__ void __launch_bounds__(EW) dec_init2_kernel(StripDev s, int side, char *ws, Slab sl, const DecState *st) {
+  const int e = blockIdx.y, M = s.M, M2 = 2 * s.M;
+  if (st[e].done) return;
+  Z *eps_s = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_S]));
+  Z *eps_r = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS_R]));
+  Z *eps = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZEPS]));
+  Z *a = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZA0]));
+  Z *b = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZB0]));
+  Z *vf = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZVF]));
+  Z *vb = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZVB]));
+  const bool left = side != 1;
+  const Z zero = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M2 * M2; i += (int64_t)gridDim.x * EW) {
+    const int r = (int)(i / M2), c = (int)(i % M2);
+    const int br = r / M, bc = c / M, rr = r % M, cc = c % M;
+    const D v = strip_V(s, rr, cc);           // V[rr][cc]
+    const D vt = strip_V(s, cc, rr);          // (V^+)[rr][cc] = conj(V[cc][rr])
+    const Z Vrc = zdd(v), Vdrc = zdd(D{vt.re, -vt.im});
+    const Z al = left ? Vrc : Vdrc, be = left ? Vdrc : Vrc;
+    Z h;
+    if (br == bc) h = zdd(ld_z(s.H0 + (int64_t)rr * M + cc));
+    else h = br == 0 ? al : be;
+    eps_s[i] = eps_r[i] = eps[i] = h;
+    a[i] = (br == 1 && bc == 0) ? al : zero;
+    b[i] = (br == 0 && bc == 1) ? be : zero;
+    vf[i] = br == bc ? al : zero;
+    vb[i] = br == bc ? be : zero;
+  }
 }
 
 // A = z - es (dd) and its FP64 copy, padded to Mp with an identity block.
-__global__ void __launch_bounds__(EW) dec_form_kernel(int M, int Mp, const double *E, double eta, char *ws, Slab sl,
-                                                      int src, const DecState *st, int check_done) {
+__global__ void __launch_bounds__(EW) dec_form_kernel(int M, int Mp, const double *E, const int *emap, double eta,
+                                                      char *ws, Slab sl, int src, const DecState *st, int check_done) {
   const int e = blockIdx.y;
-  if (check_done && st[e].done) return;
+  if (dec_skip(st, e, check_done)) return;
   const Z *es = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[src]));
   Z *A = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZA]));
   D *X64 = reinterpret_cast<D *>(slab_ptr(ws, sl, e, sl.x64));
-  const double Ez = E[e];
+  const double Ez = E[emap ? emap[e] : e];
   for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)Mp * Mp; i += (int64_t)gridDim.x * EW) {
     const int r = (int)(i / Mp), c = (int)(i % Mp);
     if (r < M && c < M) {
@@ -307,22 +373,121 @@ __global__ void dec_decide_kernel(DecState *st, int nE, double tol, int max_iter
   }
 }
 
-// sigma (FP64) from the dd product; NaN for failed energies; status words.
-__global__ void __launch_bounds__(EW) dec_store_kernel(int M, char *ws, Slab sl, int src, knit_z *sigma,
-                                                       int64_t sigma_stride, const DecState *st) {
+// sigma (FP64) from the M x M block at (off, off) of the dd product (leading
+// dimension ld) of energy emap[e] (or e); NaN for failed energies.
+__global__ void __launch_bounds__(EW) dec_store_kernel(int M, int ld, int off, char *ws, Slab sl, int src,
+                                                       knit_z *sigma, int64_t sigma_stride, const DecState *st,
+                                                       const int *emap, int check) {
   const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
   const Z *s = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[src]));
-  knit_z *out = sigma + (int64_t)e * sigma_stride;
+  knit_z *out = sigma + (int64_t)(emap ? emap[e] : e) * sigma_stride;
   const bool bad = (st[e].flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) != 0;
   const double qnan = __builtin_nan("");
-  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW)
-    st_z(out + i, bad ? D{qnan, qnan} : D{to_d(s[i].re), to_d(s[i].im)});
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW) {
+    const Z v = s[(int64_t)(off + i / M) * ld + off + i % M];
+    st_z(out + i, bad ? D{qnan, qnan} : D{to_d(v.re), to_d(v.im)});
+  }
+}
+
+// Check of the surface block (offset off, leading dimension ld) against its
+// defining equation: A = z - h - Sigma into ZA and the surface g into ZXA,
+// both [M][M]; the product R = A g - I follows.
+__global__ void __launch_bounds__(EW) dec_check_form_kernel(StripDev s, int ld, int off, const double *E,
+                                                            const int *emap, double eta, char *ws, Slab sl, int sig,
+                                                            int gsrc, const DecState *st, int check) {
+  const int e = blockIdx.y, M = s.M;
+  if (dec_skip(st, e, check)) return;
+  const Z *S = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[sig]));
+  const Z *G = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[gsrc]));
+  Z *A = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZA]));
+  Z *Gc = reinterpret_cast<Z *>(slab_ptr(ws, sl, e, sl.z[ZXA]));
+  const double Ez = E[emap ? emap[e] : e];
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW) {
+    const int r = (int)(i / M), c = (int)(i % M);
+    const int64_t o = (int64_t)(off + r) * ld + off + c;
+    Z a = c_neg(c_add(zdd(ld_z(s.H0 + i)), S[o]));
+    if (r == c) a = c_add(a, Z{dd{Ez, 0.0}, dd{eta, 0.0}});
+    A[i] = a;
+    Gc[i] = G[o];
+  }
+}
+
+// max |R| (leading parts; NaN counts as +inf) of the check product in ZR.
+__global__ void __launch_bounds__(EW) dec_resid_kernel(int M, char *ws, Slab sl, DecState *st, int check) {
+  __shared__ double red[EW / 64];
+  const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
+  const Z *R = reinterpret_cast<const Z *>(slab_ptr(ws, sl, e, sl.z[ZR]));
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW) {
+    double a = fabs(R[i].re.hi) + fabs(R[i].im.hi);
+    if (a != a) a = __builtin_inf();
+    m = fmax(m, a);
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < EW / 64; ++w) m = fmax(m, red[w]);
+    m = fmax(m, red[0]);
+    atomicMax(&st[e].resid, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// A check above RESID_TOL (or non-finite) sets `bit`; the residual is cleared.
+__global__ void dec_resid_decide_kernel(DecState *st, int n, int bit, int check) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n || dec_skip(st, e, check)) return;
+  const double r = __longlong_as_double((long long)st[e].resid);
+  if (!(r <= RESID_TOL)) st[e].flags |= bit;
+  st[e].resid = 0ull;
+}
+
+// Retry slots: energies that failed the check, in slots [0, RETRY_SLOTS) up to
+// the capacity (one thread, in energy order, so the assignment is
+// reproducible); the rest, or all of them when `allow` is 0, have failed.
+__global__ void dec_slot_assign_kernel(DecState *st, int nE, DecState *st2, int *emap, int allow) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int k = 0;
+  for (int e = 0; e < nE; ++e) {
+    if (!(st[e].flags & DEC_RETRY)) continue;
+    if (allow && k < RETRY_SLOTS) emap[k++] = e;
+    else st[e].flags |= DEC_FAILED;
+  }
+  for (int j = 0; j < RETRY_SLOTS; ++j) {
+    if (j >= k) emap[j] = -1;
+    const int e = emap[j];
+    st2[j] = e >= 0 ? DecState{0, 0, 0, 0, 0ull, st[e].scale, 0ull} : DecState{1, 0, 0, 1, 0ull, 0ull, 0ull};
+  }
+}
+
+// Results of the retry slots into the energies' states.
+__global__ void dec_slot_merge_kernel(DecState *st, const DecState *st2, const int *emap) {
+  const int j = threadIdx.x;
+  if (blockIdx.x != 0 || j >= RETRY_SLOTS) return;
+  const int e = emap[j];
+  if (e < 0) return;
+  st[e].flags = (st2[j].flags & (DEC_PUBLIC | DEC_FAILED)) | DEC_RETRY;
+  st[e].iters = st2[j].iters;
+}
+
+// NaN self-energies for the energies that failed the check for good.
+__global__ void __launch_bounds__(EW) dec_poison_kernel(int M, int nE, int nsurf, knit_z *sigma, const DecState *st) {
+  const int e = blockIdx.y;
+  if (!(st[e].flags & DEC_FAILED)) return;
+  const double qnan = __builtin_nan("");
+  for (int sf = 0; sf < nsurf; ++sf) {
+    knit_z *out = sigma + ((int64_t)sf * nE + e) * M * M;
+    for (int64_t i = blockIdx.x * (int64_t)EW + threadIdx.x; i < (int64_t)M * M; i += (int64_t)gridDim.x * EW)
+      st_z(out + i, D{qnan, qnan});
+  }
 }
 
 __global__ void dec_status_kernel(const DecState *st, int nE, int max_iter, int32_t *pstatus, int32_t *iters) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nE) return;
-  pstatus[e] = st[e].flags;
+  pstatus[e] = (st[e].flags & DEC_PUBLIC) | ((st[e].flags & DEC_FAILED) ? KNIT_P_NOCONV : 0);
   if (iters) iters[e] = st[e].iters < max_iter ? st[e].iters : max_iter;
 }
 
@@ -335,29 +500,32 @@ struct Ctx {
   Slab sl;
   char *ws;
   DecState *st;
+  const int *emap;     // slot -> energy (retry pass), or NULL
+  int gx_cap;          // GEMM grid x cap (tiles are strided over it), 0 = one block per tile
   hipStream_t stream;
   Z *zb(int i) const { return reinterpret_cast<Z *>(ws + sl.z[i]); }
+  int gx(int m) const {
+    const int tiles = ((m + GT - 1) / GT) * ((m + GT - 1) / GT);
+    return gx_cap > 0 && tiles > gx_cap ? gx_cap : tiles;
+  }
 };
 
 hipError_t gemm_zz(const Ctx &c, int a, int b, int out, double cI = 0.0, int neg = 0, int check = 1) {
-  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
-  hipLaunchKernelGGL((dd_gemm_kernel<Z, Z>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), c.zb(b),
+  hipLaunchKernelGGL((dd_gemm_kernel<Z, Z>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), c.zb(b),
                      (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
   return hipGetLastError();
 }
 
 // products with the FP64 inverse X0 as the left (dz) or right (zd) factor
 hipError_t gemm_dz(const Ctx &c, int b, int out, double cI, int neg, int check) {
-  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
   const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
-  hipLaunchKernelGGL((dd_gemm_kernel<D, Z>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, X, c.zb(b),
+  hipLaunchKernelGGL((dd_gemm_kernel<D, Z>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, X, c.zb(b),
                      (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
   return hipGetLastError();
 }
 hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) {
-  const int tiles = ((c.M + GT - 1) / GT) * ((c.M + GT - 1) / GT);
   const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
-  hipLaunchKernelGGL((dd_gemm_kernel<Z, D>), dim3(tiles, c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), X,
+  hipLaunchKernelGGL((dd_gemm_kernel<Z, D>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), X,
                      (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
   return hipGetLastError();
 }
@@ -366,14 +534,15 @@ hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) 
 // steps X <- X (2I - A X) in double-double.
 hipError_t inverse_dd(const Ctx &c, const double *E, double eta, int src, int check) {
   hipError_t err;
-  hipLaunchKernelGGL(dec_form_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.M, c.Mp, E, eta, c.ws, c.sl,
-                     src, c.st, check);
+  hipLaunchKernelGGL(dec_form_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.M, c.Mp, E, c.emap, eta, c.ws,
+                     c.sl, src, c.st, check);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const int64_t dstride = (int64_t)(c.sl.bytes / sizeof(D));
   const int sst = (int)(sizeof(DecState) / sizeof(int32_t));
   err = launch_inverse_fp64(reinterpret_cast<D *>(c.ws + c.sl.x64), dstride,
                             reinterpret_cast<D *>(c.ws + c.sl.scr), dstride, c.M,
-                            reinterpret_cast<D *>(c.ws + c.sl.xi64), dstride, check ? &c.st->done : nullptr, sst,
+                            reinterpret_cast<D *>(c.ws + c.sl.xi64), dstride,
+                            check == 1 ? &c.st->done : (check == 2 ? &c.st->skip : nullptr), sst,
                             &c.st->flags, sst, c.nE, c.stream);
   if (err != hipSuccess) return err;
   if ((err = gemm_zd(c, ZA, ZR, 2.0, 1, check)) != hipSuccess) return err;   // R  = 2I - A X0
@@ -384,30 +553,29 @@ hipError_t inverse_dd(const Ctx &c, const double *E, double eta, int src, int ch
 
 }  // namespace
 
+// Workspace: per-energy states, the retry slots' states and energy map, then
+// the slabs (the retry pass reuses the slab region after the first pass).
+static size_t head_bytes(int nE) { return (((size_t)nE * sizeof(DecState)) + 255) & ~size_t(255); }
+static size_t slot_bytes() {
+  return (((size_t)RETRY_SLOTS * (sizeof(DecState) + sizeof(int))) + 255) & ~size_t(255);
+}
+static bool retry_fits(int M) { return mfma_padded(2 * M) <= 512; }
+
 size_t decimation_workspace(int M, int nE) {
-  const size_t head = (((size_t)nE * sizeof(DecState)) + 255) & ~size_t(255);
-  return head + (size_t)nE * slab_of(M).bytes;
+  size_t slabs = (size_t)nE * slab_of(M).bytes;
+  if (retry_fits(M)) {
+    const size_t r = (size_t)RETRY_SLOTS * slab_of(2 * M).bytes;
+    if (r > slabs) slabs = r;
+  }
+  return head_bytes(nE) + slot_bytes() + slabs;
 }
 
-hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta, double tol,
-                             int max_iter, knit_z *sigma, int32_t *iters, int32_t *pstatus, void *ws,
-                             hipStream_t stream) {
-  if (nE <= 0) return hipSuccess;
-  if (mfma_padded(s.M) > 512) return hipErrorInvalidValue;
-  Ctx c;
-  c.s = s;
-  c.M = s.M;
-  c.Mp = mfma_padded(s.M);
-  c.nE = nE;
-  c.sl = slab_of(s.M);
-  c.st = reinterpret_cast<DecState *>(ws);
-  c.ws = reinterpret_cast<char *>(ws) + ((((size_t)nE * sizeof(DecState)) + 255) & ~size_t(255));
-  c.stream = stream;
-  const int both = side == 2;
+namespace {
+
+// The doubling on context c (every energy, or the retry slots): max_iter
+// steps queued without waiting; converged energies skip the rest.
+hipError_t run_doubling(const Ctx &c, const double *E, double eta, double tol, int max_iter, int both) {
   hipError_t err;
-  hipLaunchKernelGGL(dec_reset_state_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE);
-  hipLaunchKernelGGL(dec_init_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, s, side, c.ws, c.sl, c.st);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
   for (int it = 0; it < max_iter; ++it) {
     const int a = (it & 1) ? ZA1 : ZA0, b = (it & 1) ? ZB1 : ZB0;
     const int an = (it & 1) ? ZA0 : ZA1, bn = (it & 1) ? ZB0 : ZB1;
@@ -418,23 +586,83 @@ hipError_t launch_decimation(const StripDev &s, int side, const double *E, int n
     if ((err = gemm_zz(c, b, ZGA, ZT2)) != hipSuccess) return err;          // b g a
     if ((err = gemm_zz(c, a, ZGA, an)) != hipSuccess) return err;           // a g a
     if ((err = gemm_zz(c, b, ZGB, bn)) != hipSuccess) return err;           // b g b
-    hipLaunchKernelGGL(dec_update_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, c.M, c.ws, c.sl, an, bn, both,
-                       c.st);
-    hipLaunchKernelGGL(dec_decide_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE, tol, max_iter);
+    hipLaunchKernelGGL(dec_update_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.M, c.ws, c.sl, an, bn,
+                       both, c.st);
+    hipLaunchKernelGGL(dec_decide_kernel, dim3((c.nE + 255) / 256), dim3(256), 0, c.stream, c.st, c.nE, tol,
+                       max_iter);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  // surface Green functions and self-energies:
-  //   left (or the one requested): Sigma = Vf g Vb with g = (z - eps_s)^{-1}
-  //   side 2, right:               Sigma = Vb g Vf with g = (z - eps_r)^{-1}
+  return hipSuccess;
+}
+
+// Surface Green functions, self-energies and their check, for every surface:
+//   left (or the one requested): Sigma = Vf g Vb with g = (z - eps_s)^{-1}
+//   side 2, right:               Sigma = Vb g Vf with g = (z - eps_r)^{-1}
+// On the two-slice cell (cell = 1) the surface slice is the leading block
+// (left) or the trailing block (right) of dimension M.  A failed check sets
+// `bit` in the energy's (or slot's) flags.
+hipError_t surfaces(const Ctx &c, const double *E, double eta, int both, int cell, int check, knit_z *sigma,
+                    int nE_all, int bit) {
+  hipError_t err;
+  const int M = c.s.M;
   for (int surf = 0; surf < (both ? 2 : 1); ++surf) {
-    if ((err = inverse_dd(c, E, eta, surf == 0 ? ZEPS_S : ZEPS_R, 0)) != hipSuccess) return err;
-    if ((err = gemm_zz(c, surf == 0 ? ZVF : ZVB, ZXB, ZT1, 0.0, 0, 0)) != hipSuccess) return err;
-    if ((err = gemm_zz(c, ZT1, surf == 0 ? ZVB : ZVF, ZT2, 0.0, 0, 0)) != hipSuccess) return err;
-    hipLaunchKernelGGL(dec_store_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, c.M, c.ws, c.sl, (int)ZT2,
-                       sigma + (int64_t)surf * nE * c.M * c.M, (int64_t)c.M * c.M, c.st);
+    const int off = cell && surf == 1 ? M : 0;
+    if ((err = inverse_dd(c, E, eta, surf == 0 ? ZEPS_S : ZEPS_R, check)) != hipSuccess) return err;
+    if ((err = gemm_zz(c, surf == 0 ? ZVF : ZVB, ZXB, ZT1, 0.0, 0, check)) != hipSuccess) return err;
+    if ((err = gemm_zz(c, ZT1, surf == 0 ? ZVB : ZVF, ZT2, 0.0, 0, check)) != hipSuccess) return err;
+    hipLaunchKernelGGL(dec_store_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, M, c.M, off, c.ws, c.sl,
+                       (int)ZT2, sigma + (int64_t)surf * nE_all * M * M, (int64_t)M * M, c.st, c.emap, check);
+    hipLaunchKernelGGL(dec_check_form_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.s, c.M, off, E, c.emap,
+                       eta, c.ws, c.sl, (int)ZT2, (int)ZXB, c.st, check);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // R = (z - h - Sigma) g - I, [M][M]
+    Ctx cm = c;
+    cm.M = M;
+    if ((err = gemm_zz(cm, ZA, ZXA, ZR, -1.0, 0, check)) != hipSuccess) return err;
+    hipLaunchKernelGGL(dec_resid_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, M, c.ws, c.sl, c.st, check);
+    hipLaunchKernelGGL(dec_resid_decide_kernel, dim3((c.nE + 255) / 256), dim3(256), 0, c.stream, c.st, c.nE, bit,
+                       check);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  hipLaunchKernelGGL(dec_status_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, c.st, nE, max_iter, pstatus,
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta, double tol,
+                             int max_iter, knit_z *sigma, int32_t *iters, int32_t *pstatus, void *ws,
+                             hipStream_t stream) {
+  if (nE <= 0) return hipSuccess;
+  if (mfma_padded(s.M) > 512) return hipErrorInvalidValue;
+  char *base = reinterpret_cast<char *>(ws);
+  DecState *st = reinterpret_cast<DecState *>(base);
+  DecState *st2 = reinterpret_cast<DecState *>(base + head_bytes(nE));
+  int *emap = reinterpret_cast<int *>(st2 + RETRY_SLOTS);
+  char *slabs = base + head_bytes(nE) + slot_bytes();
+  const int both = side == 2;
+  hipError_t err;
+  // ---- every energy, cells of one slice
+  Ctx c{s, s.M, mfma_padded(s.M), nE, slab_of(s.M), slabs, st, nullptr, 0, stream};
+  hipLaunchKernelGGL(dec_reset_state_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, st, nE);
+  hipLaunchKernelGGL(dec_init_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, s, side, c.ws, c.sl, c.st);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if ((err = run_doubling(c, E, eta, tol, max_iter, both)) != hipSuccess) return err;
+  if ((err = surfaces(c, E, eta, both, 0, 0, sigma, nE, DEC_RETRY)) != hipSuccess) return err;
+  // ---- energies that failed the check: cells of two slices, in the retry slots
+  const bool fits = retry_fits(s.M);
+  hipLaunchKernelGGL(dec_slot_assign_kernel, dim3(1), dim3(1), 0, stream, st, nE, st2, emap, fits ? 1 : 0);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (fits) {
+    Ctx c2{s, 2 * s.M, mfma_padded(2 * s.M), RETRY_SLOTS, slab_of(2 * s.M), slabs, st2, emap, 64, stream};
+    hipLaunchKernelGGL(dec_init2_kernel, dim3(EW_BLOCKS, RETRY_SLOTS), dim3(EW), 0, stream, s, side, c2.ws, c2.sl,
+                       c2.st);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = run_doubling(c2, E, eta, tol, max_iter, both)) != hipSuccess) return err;
+    if ((err = surfaces(c2, E, eta, both, 1, 2, sigma, nE, DEC_FAILED)) != hipSuccess) return err;
+    hipLaunchKernelGGL(dec_slot_merge_kernel, dim3(1), dim3(64), 0, stream, st, st2, emap);
+  }
+  hipLaunchKernelGGL(dec_poison_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, s.M, nE, both ? 2 : 1, sigma, st);
+  hipLaunchKernelGGL(dec_status_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, st, nE, max_iter, pstatus,
                      iters);
   return hipGetLastError();
 }

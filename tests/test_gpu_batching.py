@@ -92,8 +92,8 @@ def test_lpt_order_serves_costliest_first():
     Ms = np.array([b.strips[int(s)].M for s in b.probs.host["strip"]])
     Mp = (Ms + 31) // 32 * 32
     cost = (Mp.astype(np.float64) ** 3 * b.probs.host["L"])[order]
-    # binned at four bins per octave: a later problem is never costlier by more than one bin
-    assert np.all(cost[1:] <= cost[:-1] * 2 ** 0.25 * (1 + 1e-12))
+    # binned at 16 bins per doubling: a later problem is never costlier by more than one bin
+    assert np.all(cost[1:] <= cost[:-1] * 2 ** (1 / 16) * (1 + 1e-12))
 
 
 @gpu
