@@ -39,11 +39,11 @@ METRIC = "RGF slice-steps/s at W=256, FP32-MFMA+refine vs FP64; T(E) points/s at
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp32_refine": 157.3}
 TOL_PER_CHANNEL = 1e-6
 
-# HBM bytes per launch of the FP64 sweep kernel from the calibrated FETCH_SIZE /
+# HBM bytes per launch of the projected FP64 sweep kernel (the headline step) from the calibrated FETCH_SIZE /
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "a4411341dc575ba9", "bytes": 8.1760e+13,
+    "c4": {"sha": "212eec92b93cd561", "bytes": 6.3878e+13,
            "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
 }
 
