@@ -73,7 +73,45 @@ __device__ __forceinline__ void ctile_mma(CTile<R, NBLK> &t, const cpx<R> a[NBLK
     }
 }
 
+// (16 NBR) x (16 NBC) complex accumulator of one wave (rectangular tiles)
+template <class R, int NBR, int NBC>
+struct CTileRC {
+  typename Mfma<R>::acc_t re[NBR][NBC], im[NBR][NBC];
+};
+
+// acc += a * b for one k-slice of 4, rectangular: a[NBR] row blocks, b[NBC] column blocks.
+template <class R, int NBR, int NBC>
+__device__ __forceinline__ void ctile_mma_rc(CTileRC<R, NBR, NBC> &t, const cpx<R> a[NBR], const cpx<R> b[NBC]) {
+  using M = Mfma<R>;
+#pragma unroll
+  for (int i = 0; i < NBR; ++i)
+#pragma unroll
+    for (int j = 0; j < NBC; ++j) {
+      t.re[i][j] = M::mma(a[i].re, b[j].re, t.re[i][j]);
+      t.re[i][j] = M::mma(-a[i].im, b[j].im, t.re[i][j]);
+      t.im[i][j] = M::mma(a[i].re, b[j].im, t.im[i][j]);
+      t.im[i][j] = M::mma(a[i].im, b[j].re, t.im[i][j]);
+    }
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Visit the rectangular tile's elements held by this lane (as ctile_for_each).
+template <class R, int NBR, int NBC, class F>
+__device__ __forceinline__ void ctile_for_each_rc(CTileRC<R, NBR, NBC> &t, F f) {
+  const int l = lane_id();
+#pragma unroll
+  for (int i = 0; i < NBR; ++i)
+#pragma unroll
+    for (int j = 0; j < NBC; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        R re = t.re[i][j][e], im = t.im[i][j][e];
+        f(16 * i + Mfma<R>::row(l, e), 16 * j + (l & 15), re, im);
+        t.re[i][j][e] = re;
+        t.im[i][j][e] = im;
+      }
+}
 
 // Load this lane's A operands of rows [r0, r0 + 16 NBLK), k-slice [k, k+4) of a
 // row-major complex matrix (any element type, converted to R).

@@ -300,6 +300,55 @@ __device__ __attribute__((noinline)) void tile_gemm_window_flat(
   }
 }
 
+// The rank-NO update of the rows outside the pivot rows, with 64 x 32 wave
+// tiles: X[r, c] += sum_k X[r, acol + k] X[krow0 + k, c] for the 64-row tiles
+// rows.at(i, 64) and the 32-column tiles cols.at(j, 32).  Twice the rows of
+// tile_gemm_window's tiles: the pivot-row operand (the one every row tile
+// re-reads) is read half as often.  Operands one k-slice ahead.
+template <class RG, int NT>
+__device__ __attribute__((noinline)) void tile_update_64x32(cpx<RG> *X, const int *phys, int Mp, int rb1, int rn,
+                                                            int rh, int rhl, int cb1, int cn, int ch, int chl, int K,
+                                                            int acol, int krow0) {
+  constexpr int NBR = 4, NBC = 2;
+  const RowMap rm{phys, Mp};
+  const IdxMap rows{rb1, rn, 0, rn, rh, rhl}, cols{cb1, cn, 0, cn, ch, chl};
+  const int l = lane_id();
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int ntot = rows.n * cols.n;
+  for (int it = wave; it < ntot; it += nwaves) {
+    const int r0 = rows.at(it / cols.n, 64), c0 = cols.at(it % cols.n, 32);
+    int64_t aoff[NBR];
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) aoff[i] = (int64_t)rm(r0 + 16 * i + (l & 15)) * Mp + acol + (l >> 4);
+    CTileRC<RG, NBR, NBC> acc;
+    ctile_for_each_rc<RG, NBR, NBC>(acc, [=](int r, int c, RG &re, RG &im) {
+      const cpx<RG> v = X[(int64_t)rm(r0 + r) * Mp + c0 + c];
+      re = v.re;
+      im = v.im;
+    });
+    cpx<RG> a[2][NBR], b[2][NBC];
+    auto load = [&](int ks, int buf) {
+#pragma unroll
+      for (int i = 0; i < NBR; ++i) a[buf][i] = X[aoff[i] + 4 * ks];
+      const int64_t brow = (int64_t)rm(krow0 + 4 * ks + (l >> 4)) * Mp + c0 + (l & 15);
+#pragma unroll
+      for (int j = 0; j < NBC; ++j) b[buf][j] = X[brow + 16 * j];
+    };
+    const int nks = K / 4;   // even
+    load(0, 0);
+#pragma unroll 1
+    for (int ks = 0; ks < nks; ks += 2) {
+      load(ks + 1, 1);
+      ctile_mma_rc<RG, NBR, NBC>(acc, a[0], b[0]);
+      if (ks + 2 < nks) load(ks + 2, 0);
+      ctile_mma_rc<RG, NBR, NBC>(acc, a[1], b[1]);
+    }
+    ctile_for_each_rc<RG, NBR, NBC>(acc, [=](int r, int c, RG &re, RG &im) {
+      X[(int64_t)rm(r0 + r) * Mp + c0 + c] = cpx<RG>{re, im};
+    });
+  }
+}
+
 template <class RG, int NBLK, int NT>
 __device__ __forceinline__ void tile_gemm_window(const cpx<RG> *X, cpx<RG> *S, int lds, RowMap rm, IdxMap rows,
                                                  IdxMap cols, int K, int arow, int acol, int krow0, int bshift,
@@ -376,10 +425,17 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
       X[(int64_t)rm(r) * Mp + K0 + c] = Sb[(int64_t)r * NO + c];
     }
     __syncthreads();
-    // (c) X[r, c] += X[r, K] X[P, c] (old pivot rows) for r outside P, c outside K
-    if (Mp > NOe)
-      tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, imap(0, R / 32 - NOe / 32, K0, NOe), ocols, NOe, 0, K0, K0, 0, true,
-                              false);
+    // (c) X[r, c] += X[r, K] X[P, c] (old pivot rows) for r outside P, c outside K:
+    // 64-row tiles (K0 is a multiple of 64, so none straddles P), and the last 32
+    // rows on their own when the count of 32-row tiles is odd (they follow P)
+    if (Mp > NOe) {
+      const int n32 = R / 32 - NOe / 32;
+      if (n32 >= 2)
+        tile_update_64x32<RG, NT>(X, rm.phys, Mp, 0, n32 / 2, K0, NOe, ocols.base1, ocols.n, ocols.hole,
+                                  ocols.hole_len, NOe, K0, K0);
+      if (n32 & 1)
+        tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, imap(R - 32, 1), ocols, NOe, 0, K0, K0, 0, true, false);
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < NOe * Mp; e += blockDim.x) {
       const int r = e / Mp, c = e % Mp;
