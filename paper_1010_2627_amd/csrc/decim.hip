@@ -29,9 +29,11 @@
 //
 // Work layout (every energy runs the same sequence of launches):
 //   * g_k: the FP64 inverse of z - eps_k on the matrix cores (one workgroup
-//     per energy), then two Newton steps X <- X + X (I - A X) in
-//     double-double, each of which squares the residual (1e-16 kappa -> ~1e-64
-//     kappa^4);
+//     per energy), then two Newton steps X <- X + X R, R = I - A X, each of
+//     which squares the residual (1e-16 kappa -> ~1e-64 kappa^4).  R is formed
+//     in double-double; the correction X R is small (|R| |X|), so its FP64
+//     product on the matrix cores, rounding ~1e-16 |R| |X|, stays below the
+//     |R|^2 the step leaves, and it is added to X in double-double;
 //   * every product is a batched double-double tile GEMM over (tile, energy),
 //     so all compute units share the work of every energy;
 //   * convergence is decided on the device per energy: later launches skip
@@ -55,6 +57,7 @@
 // energy gets KNIT_P_NOCONV and NaN output.
 
 #include "knit_internal.h"
+#include "knit_mfma.h"
 
 namespace knit {
 
@@ -222,6 +225,53 @@ __global__ void __launch_bounds__(GTHREADS) dd_gemm_kernel(const TA *A, const TB
         Ce[(int64_t)r * M + c] = v;
       }
   }
+}
+
+__device__ __forceinline__ D hi_of(D v) { return v; }
+__device__ __forceinline__ D hi_of(Z v) { return D{v.re.hi, v.im.hi}; }
+
+// Newton correction C_e = X_e + X_e R_e ([M][M] each energy; X double-double
+// or FP64, R double-double): the product of the FP64 leading parts on the
+// matrix cores (v_mfma_f64_16x16x4f64, four real products per complex one),
+// added to X in double-double.  One wave per 32 x 32 output tile.
+template <class TX>
+__global__ void __launch_bounds__(64) newton_corr_kernel(const TX *X, const Z *R, Z *C, int64_t stride_bytes, int M,
+                                                         const DecState *st, int check) {
+  const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
+  const int64_t eo = (int64_t)e * stride_bytes;
+  const TX *Xe = reinterpret_cast<const TX *>(reinterpret_cast<const char *>(X) + eo);
+  const Z *Re = reinterpret_cast<const Z *>(reinterpret_cast<const char *>(R) + eo);
+  Z *Ce = reinterpret_cast<Z *>(reinterpret_cast<char *>(C) + eo);
+  const int tn = (M + 31) / 32;
+  const int r0 = (int)(blockIdx.x / tn) * 32, c0 = (int)(blockIdx.x % tn) * 32;
+  const int l = threadIdx.x;
+  CTile<double, 2> acc;
+  acc.zero();
+  for (int k = 0; k < M; k += 4) {
+    cpx<double> a[2], b[2];
+    const int kk = k + (l >> 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = r0 + 16 * i + (l & 15);
+      const D v = (r < M && kk < M) ? hi_of(Xe[(int64_t)r * M + kk]) : D{0.0, 0.0};
+      a[i] = {v.re, v.im};
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = c0 + 16 * j + (l & 15);
+      const D v = (kk < M && c < M) ? hi_of(Re[(int64_t)kk * M + c]) : D{0.0, 0.0};
+      b[j] = {v.re, v.im};
+    }
+    ctile_mma<double, 2>(acc, a, b);
+  }
+  ctile_for_each<double, 2>(acc, [&](int r, int c, double &re, double &im) {
+    const int gr = r0 + r, gc = c0 + c;
+    if (gr < M && gc < M) {
+      const Z x = zdd(Xe[(int64_t)gr * M + gc]);
+      Ce[(int64_t)gr * M + gc] = Z{r_add(x.re, dd{re, 0.0}), r_add(x.im, dd{im, 0.0})};
+    }
+  });
 }
 
 __device__ __forceinline__ char *slab_ptr(char *ws, const Slab &sl, int e, size_t off) {
@@ -516,13 +566,21 @@ hipError_t gemm_zz(const Ctx &c, int a, int b, int out, double cI = 0.0, int neg
   return hipGetLastError();
 }
 
-// products with the FP64 inverse X0 as the left (dz) or right (zd) factor
-hipError_t gemm_dz(const Ctx &c, int b, int out, double cI, int neg, int check) {
-  const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
-  hipLaunchKernelGGL((dd_gemm_kernel<D, Z>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, X, c.zb(b),
-                     (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
+// Newton corrections out = X + X R on the matrix cores, X the FP64 inverse X0
+// (x0 = true) or the double-double buffer x
+hipError_t newton_corr(const Ctx &c, bool x0, int x, int r, int out, int check) {
+  const int tn = (c.M + 31) / 32;
+  if (x0)
+    hipLaunchKernelGGL((newton_corr_kernel<D>), dim3(tn * tn, c.nE), dim3(64), 0, c.stream,
+                       reinterpret_cast<const D *>(c.ws + c.sl.xi64), c.zb(r), c.zb(out), (int64_t)c.sl.bytes, c.M,
+                       c.st, check);
+  else
+    hipLaunchKernelGGL((newton_corr_kernel<Z>), dim3(tn * tn, c.nE), dim3(64), 0, c.stream, c.zb(x), c.zb(r),
+                       c.zb(out), (int64_t)c.sl.bytes, c.M, c.st, check);
   return hipGetLastError();
 }
+
+// products with the FP64 inverse X0 as the right factor
 hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) {
   const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
   hipLaunchKernelGGL((dd_gemm_kernel<Z, D>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), X,
@@ -531,7 +589,8 @@ hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) 
 }
 
 // g = (z - es)^{-1} into ZXB: FP64 matrix-core inverse X0, then two Newton
-// steps X <- X (2I - A X) in double-double.
+// steps X <- X + X R with the residual R = I - A X in double-double and the
+// correction X R on the matrix cores.
 hipError_t inverse_dd(const Ctx &c, const double *E, double eta, int src, int check) {
   hipError_t err;
   hipLaunchKernelGGL(dec_form_kernel, dim3(EW_BLOCKS, c.nE), dim3(EW), 0, c.stream, c.M, c.Mp, E, c.emap, eta, c.ws,
@@ -545,10 +604,10 @@ hipError_t inverse_dd(const Ctx &c, const double *E, double eta, int src, int ch
                             check == 1 ? &c.st->done : (check == 2 ? &c.st->skip : nullptr), sst,
                             &c.st->flags, sst, c.nE, c.stream);
   if (err != hipSuccess) return err;
-  if ((err = gemm_zd(c, ZA, ZR, 2.0, 1, check)) != hipSuccess) return err;   // R  = 2I - A X0
-  if ((err = gemm_dz(c, ZR, ZXA, 0.0, 0, check)) != hipSuccess) return err;  // XA = X0 R
-  if ((err = gemm_zz(c, ZA, ZXA, ZR, 2.0, 1, check)) != hipSuccess) return err;   // R  = 2I - A XA
-  return gemm_zz(c, ZXA, ZR, ZXB, 0.0, 0, check);                                // XB = XA R
+  if ((err = gemm_zd(c, ZA, ZR, 1.0, 1, check)) != hipSuccess) return err;        // R  = I - A X0
+  if ((err = newton_corr(c, true, 0, ZR, ZXA, check)) != hipSuccess) return err;  // XA = X0 + X0 R
+  if ((err = gemm_zz(c, ZA, ZXA, ZR, 1.0, 1, check)) != hipSuccess) return err;   // R  = I - A XA
+  return newton_corr(c, false, ZXA, ZR, ZXB, check);                             // XB = XA + XA R
 }
 
 }  // namespace
