@@ -349,6 +349,68 @@ __device__ __attribute__((noinline)) void tile_update_64x32(cpx<RG> *X, const in
   }
 }
 
+// The update inside an outer panel after its inner panel at k0:
+//   X[r, c] += sum_{k < 16} X[r, k0 + k] X[k0 + k, c]
+// for the 16-row tiles rows.at(i, 16) and 16-column tiles cols.at(j, 16).  A
+// wave takes a row strip, keeps its 16 x 16 multipliers in registers and walks
+// the column tiles, loading the next tile's accumulator and pivot-row block
+// while the current tile's products run (same products, in the same order, as
+// tile_gemm_window with one 16 x 16 block).
+template <class RG, int NT>
+__device__ __attribute__((noinline)) void inner_update_strips(cpx<RG> *X, const int *phys, int Mp, int rb1, int rn,
+                                                              int rh, int rhl, int cb1, int cn, int ch, int chl,
+                                                              int k0) {
+  using M = Mfma<RG>;
+  const RowMap rm{phys, Mp};
+  const IdxMap rows{rb1, rn, 0, rn, rh, rhl}, cols{cb1, cn, 0, cn, ch, chl};
+  const int l = lane_id();
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  int64_t brow[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) brow[ks] = (int64_t)rm(k0 + 4 * ks + (l >> 4)) * Mp + (l & 15);
+  for (int it = wave; it < rows.n; it += nwaves) {
+    const int r0 = rows.at(it, 16);
+    cpx<RG> a[4][1];
+    const int64_t arow = (int64_t)rm(r0 + (l & 15)) * Mp + k0 + (l >> 4);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks][0] = X[arow + 4 * ks];
+    int64_t crow[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) crow[e] = (int64_t)rm(r0 + M::row(l, e)) * Mp + (l & 15);
+    cpx<RG> cb[2][4], bb[2][4][1];
+    auto load = [&](int j, int buf) {
+      const int c0 = cols.at(j, 16);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cb[buf][e] = X[crow[e] + c0];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) bb[buf][ks][0] = X[brow[ks] + c0];
+    };
+    auto step = [&](int j, int buf) {
+      CTile<RG, 1> acc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc.re[0][0][e] = cb[buf][e].re;
+        acc.im[0][0][e] = cb[buf][e].im;
+      }
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) ctile_mma<RG, 1>(acc, a[ks], bb[buf][ks]);
+      const int c0 = cols.at(j, 16);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) X[crow[e] + c0] = cpx<RG>{acc.re[0][0][e], acc.im[0][0][e]};
+    };
+    load(0, 0);
+#pragma unroll 1
+    for (int j = 0; j < cols.n; j += 2) {
+      if (j + 1 < cols.n) load(j + 1, 1);
+      step(j, 0);
+      if (j + 1 < cols.n) {
+        if (j + 2 < cols.n) load(j + 2, 0);
+        step(j + 1, 1);
+      }
+    }
+  }
+}
+
 template <class RG, int NBLK, int NT>
 __device__ __forceinline__ void tile_gemm_window(const cpx<RG> *X, cpx<RG> *S, int lds, RowMap rm, IdxMap rows,
                                                  IdxMap cols, int K, int arow, int acol, int krow0, int bshift,
@@ -393,9 +455,14 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
         tile_gemm_window<RG, BI, NT>(X, nullptr, 0, rm, imap(K0, pi), imap(k0, 1), NI, 0, k0, k0, 0, false, true);
       __syncthreads();
       // update inside the outer panel: rows [K0, Mp) minus the pivot rows
-      if (npan > 1)
-        tile_gemm_window<RG, BI, NT>(X, nullptr, 0, rm, imap(K0, (Mp - K0) / NI - 1, k0, NI), pcols, NI, 0, k0, k0, 0,
-                                 true, false);
+      if (npan > 1) {
+        if constexpr (NI == 16)
+          inner_update_strips<RG, NT>(X, phys, Mp, K0, (Mp - K0) / NI - 1, k0, NI, pcols.base1, pcols.n, pcols.hole,
+                                      pcols.hole_len, k0);
+        else
+          tile_gemm_window<RG, BI, NT>(X, nullptr, 0, rm, imap(K0, (Mp - K0) / NI - 1, k0, NI), pcols, NI, 0, k0, k0,
+                                   0, true, false);
+      }
       // pivot rows across the outer panel (into Sd: in place would race)
       if (npan > 1)
         tile_gemm_window<RG, BI, NT>(X, Sd, Mp, rm, imap(0, 1), pcols, NI, k0, k0, k0, 0, false, false);
