@@ -300,18 +300,22 @@ __device__ __attribute__((noinline)) void tile_gemm_window_flat(
   }
 }
 
-// The rank-NO update of the rows outside the pivot rows, with 64 x 32 wave
-// tiles: X[r, c] += sum_k X[r, acol + k] X[krow0 + k, c] for the 64-row tiles
-// rows.at(i, 64) and the 32-column tiles cols.at(j, 32).  Twice the rows of
-// tile_gemm_window's tiles: the pivot-row operand (the one every row tile
-// re-reads) is read half as often.  Operands one k-slice ahead.
-template <class RG, int NT>
-__device__ __attribute__((noinline)) void tile_update_64x32(cpx<RG> *X, const int *phys, int Mp, int rb1, int rn,
-                                                            int rh, int rhl, int cb1, int cn, int ch, int chl, int K,
-                                                            int acol, int krow0) {
+// Block products of the outer update with 64 x 32 wave tiles, for the 64-row
+// tiles rows.at(i, 64) and 32-column tiles cols.at(j, 32):
+//   out[r, c] = (negate ? -1 : 1) * sum_k X[arow + r, acol + k] X[krow0 + k, c + bshift]  (+ out if accumulate)
+// with out X (rows mapped) or the scratch S (leading dimension lds).  Twice the
+// rows of tile_gemm_window's tiles: the operand every row tile re-reads (pivot
+// rows, or the panel's own block) is read half as often.  K is a multiple of 32.
+// The output target and sign are template parameters: each instance keeps
+// its k-loop within the register budget.
+template <class RG, int NT, bool TO_S, bool ACC, bool NEG>
+__device__ __attribute__((noinline)) void tile_gemm_64x32(cpx<RG> *X, cpx<RG> *S, int lds, const int *phys, int Mp,
+                                                          int rb1, int rn1, int rb2, int rn, int rh, int rhl, int cb1,
+                                                          int cn, int ch, int chl, int K, int arow, int acol,
+                                                          int krow0, int bshift) {
   constexpr int NBR = 4, NBC = 2;
   const RowMap rm{phys, Mp};
-  const IdxMap rows{rb1, rn, 0, rn, rh, rhl}, cols{cb1, cn, 0, cn, ch, chl};
+  const IdxMap rows{rb1, rn1, rb2, rn, rh, rhl}, cols{cb1, cn, 0, cn, ch, chl};
   const int l = lane_id();
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int ntot = rows.n * cols.n;
@@ -319,32 +323,49 @@ __device__ __attribute__((noinline)) void tile_update_64x32(cpx<RG> *X, const in
     const int r0 = rows.at(it / cols.n, 64), c0 = cols.at(it % cols.n, 32);
     int64_t aoff[NBR];
 #pragma unroll
-    for (int i = 0; i < NBR; ++i) aoff[i] = (int64_t)rm(r0 + 16 * i + (l & 15)) * Mp + acol + (l >> 4);
+    for (int i = 0; i < NBR; ++i) aoff[i] = (int64_t)rm(arow + r0 + 16 * i + (l & 15)) * Mp + acol + (l >> 4);
+    auto dst_of = [=](int r, int c) -> cpx<RG> * {
+      if constexpr (TO_S) return S + (int64_t)(r0 + r) * lds + c0 + c;
+      else return X + (int64_t)rm(r0 + r) * Mp + c0 + c;
+    };
     CTileRC<RG, NBR, NBC> acc;
     ctile_for_each_rc<RG, NBR, NBC>(acc, [=](int r, int c, RG &re, RG &im) {
-      const cpx<RG> v = X[(int64_t)rm(r0 + r) * Mp + c0 + c];
-      re = v.re;
-      im = v.im;
+      if constexpr (ACC) {
+        const cpx<RG> v = *dst_of(r, c);
+        re = v.re;
+        im = v.im;
+      } else {
+        re = RG(0);
+        im = RG(0);
+      }
     });
-    cpx<RG> a[2][NBR], b[2][NBC];
-    auto load = [&](int ks, int buf) {
+    // operands in chunks of two k-slices, double-buffered: the loads of chunk
+    // c + 1 are in flight while the 64 products of chunk c run
+    cpx<RG> a[2][2][NBR], b[2][2][NBC];
+    auto load = [&](int ch, int buf) {
 #pragma unroll
-      for (int i = 0; i < NBR; ++i) a[buf][i] = X[aoff[i] + 4 * ks];
-      const int64_t brow = (int64_t)rm(krow0 + 4 * ks + (l >> 4)) * Mp + c0 + (l & 15);
+      for (int q2 = 0; q2 < 2; ++q2) {
+        const int ks = 2 * ch + q2;
 #pragma unroll
-      for (int j = 0; j < NBC; ++j) b[buf][j] = X[brow + 16 * j];
+        for (int i = 0; i < NBR; ++i) a[buf][q2][i] = X[aoff[i] + 4 * ks];
+        const int64_t brow = (int64_t)rm(krow0 + 4 * ks + (l >> 4)) * Mp + c0 + bshift + (l & 15);
+#pragma unroll
+        for (int j = 0; j < NBC; ++j) b[buf][q2][j] = X[brow + 16 * j];
+      }
     };
-    const int nks = K / 4;   // even
+    const int nch = K / 8;   // even
     load(0, 0);
 #pragma unroll 1
-    for (int ks = 0; ks < nks; ks += 2) {
-      load(ks + 1, 1);
-      ctile_mma_rc<RG, NBR, NBC>(acc, a[0], b[0]);
-      if (ks + 2 < nks) load(ks + 2, 0);
-      ctile_mma_rc<RG, NBR, NBC>(acc, a[1], b[1]);
+    for (int ch = 0; ch < nch; ch += 2) {
+      load(ch + 1, 1);
+#pragma unroll
+      for (int q2 = 0; q2 < 2; ++q2) ctile_mma_rc<RG, NBR, NBC>(acc, a[0][q2], b[0][q2]);
+      if (ch + 2 < nch) load(ch + 2, 0);
+#pragma unroll
+      for (int q2 = 0; q2 < 2; ++q2) ctile_mma_rc<RG, NBR, NBC>(acc, a[1][q2], b[1][q2]);
     }
     ctile_for_each_rc<RG, NBR, NBC>(acc, [=](int r, int c, RG &re, RG &im) {
-      X[(int64_t)rm(r0 + r) * Mp + c0 + c] = cpx<RG>{re, im};
+      *dst_of(r, c) = NEG ? cpx<RG>{-re, -im} : cpx<RG>{re, im};
     });
   }
 }
@@ -479,12 +500,27 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     const int n_above = K0 / 32, n_below = (R - Mp) / 32;
     const IdxMap ocols = imap(0, (Mp - NOe) / 32, K0, NOe);
     // (b) multipliers of the rows outside [K0, Mp): Sb = -X[r, K] T
-    if (n_above + n_below > 0)
-      tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap2(0, n_above, Mp, n_above + n_below), imap(0, NOe / 32), NOe, 0,
-                              K0, K0, K0, false, true);
-    // (d) new pivot rows: Sd = T X[P, c] for c outside the panel
-    if (Mp > NOe)
-      tile_gemm_window<RG, 2, NT>(X, Sd, Mp, rm, imap(0, NOe / 32), ocols, NOe, K0, K0, K0, 0, false, false);
+    // (64-row tiles: the rows above P come in pairs of 32, the rows below Mp
+    // too except an odd last 32, which the 32 x 32 routine takes)
+    if (n_above + n_below > 0) {
+      const int a64 = n_above / 2, b64 = n_below / 2;
+      if (a64 + b64 > 0)
+        tile_gemm_64x32<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0, NOe / 32,
+                                                   0, 0, NOe, 0, K0, K0, K0);
+      if (n_below & 1)
+        tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap(R - 32, 1), imap(0, NOe / 32), NOe, 0, K0, K0, K0, false,
+                                true);
+    }
+    // (d) new pivot rows: Sd = T X[P, c] for c outside the panel (64-row tiles
+    // when the panel width allows)
+    if (Mp > NOe) {
+      if (NOe % 64 == 0)
+        tile_gemm_64x32<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
+                                                    ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, K0, K0, K0,
+                                                    0);
+      else
+        tile_gemm_window<RG, 2, NT>(X, Sd, Mp, rm, imap(0, NOe / 32), ocols, NOe, K0, K0, K0, 0, false, false);
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < (n_above + n_below) * 32 * NOe; e += blockDim.x) {
       const int rr = e / NOe, c = e % NOe;
@@ -498,8 +534,9 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     if (Mp > NOe) {
       const int n32 = R / 32 - NOe / 32;
       if (n32 >= 2)
-        tile_update_64x32<RG, NT>(X, rm.phys, Mp, 0, n32 / 2, K0, NOe, ocols.base1, ocols.n, ocols.hole,
-                                  ocols.hole_len, NOe, K0, K0);
+        tile_gemm_64x32<RG, NT, false, true, false>(X, nullptr, 0, rm.phys, Mp, 0, n32 / 2, 0, n32 / 2, K0, NOe,
+                                                    ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, 0, K0, K0,
+                                                    0);
       if (n32 & 1)
         tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, imap(R - 32, 1), ocols, NOe, 0, K0, K0, 0, true, false);
     }
