@@ -500,21 +500,28 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     const int n_above = K0 / 32, n_below = (R - Mp) / 32;
     const IdxMap ocols = imap(0, (Mp - NOe) / 32, K0, NOe);
     // (b) multipliers of the rows outside [K0, Mp): Sb = -X[r, K] T
-    // (64-row tiles: the rows above P come in pairs of 32, the rows below Mp
-    // too except an odd last 32, which the 32 x 32 routine takes)
+    // (64-row tiles where there are at least two per wave: the rows above P
+    // come in pairs of 32, the rows below Mp too except an odd last 32, which
+    // the 32 x 32 routine takes; otherwise 32 x 32 tiles throughout)
+    constexpr int NW = NT / 64;
     if (n_above + n_below > 0) {
       const int a64 = n_above / 2, b64 = n_below / 2;
-      if (a64 + b64 > 0)
-        tile_gemm_64x32<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0, NOe / 32,
-                                                   0, 0, NOe, 0, K0, K0, K0);
-      if (n_below & 1)
-        tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap(R - 32, 1), imap(0, NOe / 32), NOe, 0, K0, K0, K0, false,
-                                true);
+      if ((a64 + b64) * (NOe / 32) < 2 * NW)
+        tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap2(0, n_above, Mp, n_above + n_below), imap(0, NOe / 32), NOe,
+                                0, K0, K0, K0, false, true);
+      else {
+        if (a64 + b64 > 0)
+          tile_gemm_64x32<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0,
+                                                     NOe / 32, 0, 0, NOe, 0, K0, K0, K0);
+        if (n_below & 1)
+          tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap(R - 32, 1), imap(0, NOe / 32), NOe, 0, K0, K0, K0, false,
+                                  true);
+      }
     }
     // (d) new pivot rows: Sd = T X[P, c] for c outside the panel (64-row tiles
-    // when the panel width allows)
+    // when the panel width allows and there are at least two per wave)
     if (Mp > NOe) {
-      if (NOe % 64 == 0)
+      if (NOe % 64 == 0 && (NOe / 64) * ocols.n >= 2 * NW)
         tile_gemm_64x32<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
                                                     ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, K0, K0, K0,
                                                     0);
@@ -529,16 +536,19 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     }
     __syncthreads();
     // (c) X[r, c] += X[r, K] X[P, c] (old pivot rows) for r outside P, c outside K:
-    // 64-row tiles (K0 is a multiple of 64, so none straddles P), and the last 32
-    // rows on their own when the count of 32-row tiles is odd (they follow P)
+    // 64-row tiles where there are at least two per wave (K0 is a multiple of
+    // 64, so none straddles P), and the last 32 rows on their own when the
+    // count of 32-row tiles is odd (they follow P); otherwise 32 x 32 tiles
     if (Mp > NOe) {
       const int n32 = R / 32 - NOe / 32;
-      if (n32 >= 2)
-        tile_gemm_64x32<RG, NT, false, true, false>(X, nullptr, 0, rm.phys, Mp, 0, n32 / 2, 0, n32 / 2, K0, NOe,
-                                                    ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, 0, K0, K0,
-                                                    0);
-      if (n32 & 1)
-        tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, imap(R - 32, 1), ocols, NOe, 0, K0, K0, 0, true, false);
+      const bool tall = (n32 / 2) * ocols.n >= 2 * NW;
+      const int n64 = tall ? n32 / 2 : 0;
+      const IdxMap rest = tall ? imap(R - 32, n32 & 1) : imap(0, n32, K0, NOe);
+      if (n64 > 0)
+        tile_gemm_64x32<RG, NT, false, true, false>(X, nullptr, 0, rm.phys, Mp, 0, n64, 0, n64, K0, NOe, ocols.base1,
+                                                    ocols.n, ocols.hole, ocols.hole_len, NOe, 0, K0, K0, 0);
+      if (rest.n > 0)
+        tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, rest, ocols, NOe, 0, K0, K0, 0, true, false);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < NOe * Mp; e += blockDim.x) {
