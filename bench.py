@@ -43,7 +43,7 @@ TOL_PER_CHANNEL = 1e-6
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "a93fe60cdfec89c2", "bytes": 5.6490e+13,
+    "c4": {"sha": "6514e95cf718e204", "bytes": 5.6521e+13,
            "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
 }
 
