@@ -249,3 +249,34 @@ def test_projected_full_size_spinful_w256():
         res = OR.rgf_forward(st.H0, V, b.realizations[ri].onsite, E, sL[ei:ei + 1], sR[ei:ei + 1])
         Tref = OR.transmission_lr(sL[ei:ei + 1], sR[ei:ei + 1], res["G1N"])[0]
         assert abs(T[p] - Tref) <= 1e-10 * max(1.0, abs(Tref)), (p, T[p], Tref)
+
+
+@gpu
+def test_mid_size_odd_tile_counts_match_oracle():
+    """Slice dim 416 (512 threads, 128-wide outer panels): the whole-G_1n sweep has 13 bottom
+    tiles of 32 rows and the projected one, with Gamma_L of rank 77, has 3, so both use 64-row
+    tiles next to a single trailing 32-row tile in the outer products.  Both against the
+    oracle's T at 1e-10, with seeded synthetic boundary terms."""
+    from paper_1010_2627_amd import workload
+    from oracle import rgf as OR
+    b = workload.square_batch(416, 5, 1.0, 2, 1)
+    st = b.strips[0]
+    E = b.energies[0]
+    sL = inputs.synthetic_sigma(st.M, len(E), rank=77)
+    sR = inputs.synthetic_sigma(st.M, len(E), seed=inputs.SEED_SYNTHETIC_SIGMA + 1)
+    b.set_sigmas([sL], [sR])
+    b.compute_gamma_factors()
+    G1Np, _, status_p = b.sweep_projected()
+    Tp = b.transmission_projected(G1Np)
+    G1N, _, _, status = b.sweep("fp64", gnn=False)
+    T = b.transmission(G1N)[0]
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0 and int(status_p.abs().sum()) == 0
+    assert torch.all(b.rankL == 77)
+    res = OR.rgf_forward(st.H0, st.V_dense(), b.realizations[0].onsite, E, sL, sR)
+    Tref = OR.transmission_lr(sL, sR, res["G1N"])
+    for got in (T.cpu().numpy(), Tp.cpu().numpy()):
+        assert np.max(np.abs(got - Tref) / np.maximum(1.0, np.abs(Tref))) <= 1e-10, (got, Tref)
+    for p in range(b.P):
+        ref = res["G1N"][p]
+        assert np.max(np.abs(b.block(G1N, p).cpu().numpy() - ref)) <= 1e-10 * max(1.0, np.abs(ref).max())
