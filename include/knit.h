@@ -179,7 +179,8 @@ int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E,
  *   wg_per_cu  resident workgroups per compute unit the grid is sized for (1, 2)
  *   order      0: problems in table order; 1: longest (Mp^3 L) first
  *   outer      outer panel width of the blocked elimination, 64 or 128 (each
- *              outer panel is one read-and-write pass over the slice matrix)
+ *              outer panel is one read-and-write pass over the slice matrix;
+ *              default 128 from Mp = 128, else 64)
  *
  * Process-wide; set before the sweeps that should use it (calls that run
  * concurrently with a change see either the old or the new entry).

@@ -976,7 +976,7 @@ inverse_fp64_kernel(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64
   cpx<double> *Xe = X + (int64_t)e * xstride;
   cpx<double> *Sb = scratch + (int64_t)e * sstride;
   cpx<double> *Sd = Sb + (int64_t)2 * Mp * NO_MAX;
-  const int fl = Mp >= 384 ? gj_two_level<double, NT, 128>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
+  const int fl = Mp >= 128 ? gj_two_level<double, NT, 128>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
                            : gj_two_level<double, NT, 64>(Xe, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
   for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
   __syncthreads();
@@ -1271,7 +1271,7 @@ knit_sweep_tuning sweep_default_tuning(int Mpmax) {
   t.threads = Mpmax <= 256 ? 256 : 512;
   t.wg_per_cu = Mpmax <= 256 ? 2 : 1;
   t.order = 1;
-  t.outer = Mpmax >= 384 ? 128 : 64;
+  t.outer = Mpmax >= 128 ? 128 : 64;
   return t;
 }
 

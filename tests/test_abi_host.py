@@ -175,9 +175,9 @@ def test_sweep_tuning_table_round_trip(K):
     T = K.KnitSweepTuning
     out = T()
     # defaults: 256 threads and two workgroups per unit up to Mp = 256, then 512 threads, one per
-    # unit; outer panels of 64 below Mp = 384, else 128
+    # unit; outer panels of 64 below Mp = 128, else 128
     assert f_get(K.KNIT_FP64, 3, ctypes.byref(out)) == K.KNIT_OK            # Mp = 128
-    assert (out.threads, out.wg_per_cu, out.order, out.outer) == (256, 2, 1, 64)
+    assert (out.threads, out.wg_per_cu, out.order, out.outer) == (256, 2, 1, 128)
     assert f_get(K.KNIT_FP64, 15, ctypes.byref(out)) == K.KNIT_OK           # Mp = 512
     assert (out.threads, out.wg_per_cu, out.order, out.outer) == (512, 1, 1, 128)
     # bad arguments
@@ -193,9 +193,9 @@ def test_sweep_tuning_table_round_trip(K):
     # round trip, then reset to the default
     assert f_set(K.KNIT_FP32_REFINE, 3, ctypes.byref(T(512, 1, 0, 128))) == K.KNIT_OK
     assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 512, "wg_per_cu": 1, "order": 0, "outer": 128}
-    assert K.knit_sweep_tuning_get("fp64", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 64}
+    assert K.knit_sweep_tuning_get("fp64", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 128}
     K.knit_sweep_tuning_set("fp32_refine", 3, None)
-    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 64}
+    assert K.knit_sweep_tuning_get("fp32_refine", 3) == {"threads": 256, "wg_per_cu": 2, "order": 1, "outer": 128}
 
 
 def test_autotune_candidates_and_json(K, tmp_path):
