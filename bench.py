@@ -43,7 +43,7 @@ TOL_PER_CHANNEL = 1e-6
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "6514e95cf718e204", "bytes": 5.6521e+13,
+    "c4": {"sha": "5feff3ebfd31fe92", "bytes": 5.6522e+13,
            "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
 }
 
@@ -367,6 +367,7 @@ def main():
         progress(f"ldos: {tl:.2f} s for {steps_l} slice-steps")
 
     achieved = flops_proj / twp / 1e12
+    sweep_threads = knit.knit_sweep_tuning_get("fp64", knit.tuning_class((M + 31) // 32 * 32))["threads"]
     tr = MEASURED_TRAFFIC.get(args.workload)
     traffic = tr["bytes"] if tr and tr["sha"] == sweep_source_sha() else None
     out = {
@@ -396,7 +397,8 @@ def main():
                      "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (calibrated counters)",
                      "traffic_source": tr["profile"] if traffic else None,
-                     "kernel": "sweep_mfma_kernel<double, double, false, 512, true> (FP64 MFMA, projected)",
+                     "kernel": f"sweep_mfma_kernel<double, double, false, {sweep_threads}, true> (FP64 MFMA, "
+                               f"projected)",
                      "flops_per_slice_step": "8*M^3 + 8*M^2*r (inverse + projected propagator, r = rank "
                                              "Gamma_L)",
                      "flops_per_step": flops_proj},
