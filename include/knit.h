@@ -14,7 +14,9 @@
  * conductance).  The basic recursive Green function algorithm (section 1)
  * adds the slices one at a time from the left lead to the right lead; the
  * local density of states comes from the reverse sweep (the "sewing" of
- * section 5.3-D).
+ * section 5.3-D).  Since Gamma_L = C_L C_L^+ has the rank of the lead's open
+ * channels, the recursion can carry C_L^+ G_1n (that many rows) instead of
+ * G_1n: T = || C_L^+ G_1L C_R ||_F^2 (the projected calls below).
  *
  * Conventions shared by every entry point
  *   - Complex numbers are interleaved (re, im) doubles: knit_z, the element
