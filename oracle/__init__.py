@@ -17,6 +17,9 @@ Contents
 ``dense``   brute force: the retarded Green function of the whole finite
             system by one dense inverse (plain definition, section 2.3 Eq. (2)),
             for tiny systems and for the worked example of section 2.2.
+``noise``   transmission eigenvalues (eigenvalues of t t^dagger with
+            t = Gamma_R^{1/2} G_N1 Gamma_L^{1/2}) and the shot-noise Fano
+            factor, section 2.1 item (a).
 
 Every function names the passage it follows.  Parity status: every function is
 pinned by a test in ``tests/test_oracle_*.py`` against closed forms, brute
@@ -29,10 +32,12 @@ from .leads import (surface_gf_decimation, sigma_left, sigma_right, sigma_square
 from .rgf import (rgf_forward, transmission_lr, transmission_rl, transmission_ward, ldos_rgf,
                   slice_hamiltonians, transmission_full)
 from .dense import dense_green, dense_strip_hamiltonian, dense_transmission, dense_ldos
+from .noise import psd_sqrt, transmission_amplitude, transmission_eigenvalues, fano_factor
 
 __all__ = [
     "surface_gf_decimation", "sigma_left", "sigma_right", "sigma_square_modal", "sigma_modes",
     "sigma_chain_closed_form", "n_open_square", "gamma_of", "rgf_forward", "transmission_lr",
     "transmission_rl", "transmission_ward", "ldos_rgf", "slice_hamiltonians", "transmission_full",
     "dense_green", "dense_strip_hamiltonian", "dense_transmission", "dense_ldos",
+    "psd_sqrt", "transmission_amplitude", "transmission_eigenvalues", "fano_factor",
 ]
