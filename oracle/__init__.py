@@ -17,6 +17,10 @@ Contents
 ``dense``   brute force: the retarded Green function of the whole finite
             system by one dense inverse (plain definition, section 2.3 Eq. (2)),
             for tiny systems and for the worked example of section 2.2.
+``lesser``  the lesser Green function of injection from one lead,
+            G_l^< = i G Gamma_l G^dagger (section 2.3), and the local
+            observables built on it: injected density and spin (on-site
+            blocks), longitudinal and transverse currents into every site.
 ``noise``   transmission eigenvalues (eigenvalues of t t^dagger with
             t = Gamma_R^{1/2} G_N1 Gamma_L^{1/2}) and the shot-noise Fano
             factor, section 2.1 item (a).
@@ -33,6 +37,7 @@ from .rgf import (rgf_forward, transmission_lr, transmission_rl, transmission_wa
                   slice_hamiltonians, transmission_full)
 from .dense import dense_green, dense_strip_hamiltonian, dense_transmission, dense_ldos
 from .noise import psd_sqrt, transmission_amplitude, transmission_eigenvalues, fano_factor
+from .lesser import strip_green_dense, injected_spectral, local_observables
 
 __all__ = [
     "surface_gf_decimation", "sigma_left", "sigma_right", "sigma_square_modal", "sigma_modes",
@@ -40,4 +45,5 @@ __all__ = [
     "transmission_rl", "transmission_ward", "ldos_rgf", "slice_hamiltonians", "transmission_full",
     "dense_green", "dense_strip_hamiltonian", "dense_transmission", "dense_ldos",
     "psd_sqrt", "transmission_amplitude", "transmission_eigenvalues", "fano_factor",
+    "strip_green_dense", "injected_spectral", "local_observables",
 ]
