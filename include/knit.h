@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KNIT_ABI_VERSION 2
+#define KNIT_ABI_VERSION 3
 #define KNIT_MAX_STRIPS 64     /* strip classes per batch */
 #define KNIT_MAX_M 1024        /* largest slice dimension */
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
@@ -70,16 +70,21 @@ enum {
   KNIT_P_NOCONV = 2,        /* decimation hit max_iter before convergence */
   KNIT_P_NONFINITE = 4,     /* NaN or Inf met in inputs or intermediates */
   KNIT_P_FALLBACK = 8       /* KNIT_FP32_REFINE only: a slice's FP32 inverse was too
-                               poor for one refinement step (largest residual entry above
-                               the refine threshold), so the problem was recomputed by
-                               the FP64 sweep in the same call; its outputs are FP64's */
+                               poor for the refinement (see knit_set_refine_threshold),
+                               so the problem was recomputed by the FP64 sweep in the
+                               same call; its outputs are FP64's */
 };
 
 /* Arithmetic of the slice sweep. */
 enum {
   KNIT_FP64 = 0,            /* FP64 throughout */
-  KNIT_FP32_REFINE = 1,     /* FP32 slice inverse and products, one FP64-residual
-                               refinement step on every slice inverse */
+  KNIT_FP32_REFINE = 1,     /* FP32 slice inverse X0, refined by Newton steps with FP64
+                               residuals (X <- X + X (I - A_n X), residual product in
+                               FP64) until ||I - A_n X||_F <= 1e-5; every quantity
+                               carried from slice to slice
+                               (g_n, G_1n, G_n1, the projected rows) is kept in FP64
+                               and the propagator is an FP64 product of the refined
+                               inverse */
   KNIT_FP32 = 2             /* FP32 slice inverse and products, no refinement */
 };
 
@@ -88,10 +93,19 @@ enum {
  *   M     slice dimension W * norb (1 <= M <= KNIT_MAX_M)
  *   norb  orbitals per site (1 <= norb <= KNIT_MAX_NORB, M % norb == 0)
  *   H0    device [M][M]  clean intra-slice Hamiltonian (Hermitian)
- *   vcol  device [W]     for each site a of slice n, the site of slice n-1 it
- *                        is bonded to, or -1; no site of slice n-1 may appear
- *                        twice (V is block-monomial)
- *   vblk  device [W][norb][norb]  the hopping block H_{n,n-1}(a, vcol[a])
+ *   V     device [M][M]  dense inter-slice hopping H_{n,n-1} (any matrix: the
+ *                        hopping matrices of Eq. (1) are general), or NULL: V is
+ *                        then block-monomial and given by vcol / vblk.  With a
+ *                        dense V the slice recursion forms V g V^+, G V^+ and V G
+ *                        as complex matrix products; M > 512 returns
+ *                        KNIT_E_UNSUPPORTED for it in the sweeps and the LDOS
+ *   vcol  device [W]     (V == NULL) for each site a of slice n, the site of
+ *                        slice n-1 it is bonded to, or -1; no site of slice n-1
+ *                        may appear twice (V is block-monomial)
+ *   vblk  device [W][norb][norb]  (V == NULL) the hopping block H_{n,n-1}(a, vcol[a])
+ *   onsite_dense  0: each slice's on-site term D_n is given as W site blocks
+ *                 [W][norb][norb]; 1: as a full [M][M] matrix (e.g. site-mixing
+ *                 terms, or a basis rotation of a disordered strip)
  */
 typedef struct knit_strip {
   int32_t M;
@@ -99,6 +113,9 @@ typedef struct knit_strip {
   const knit_z *H0;
   const int32_t *vcol;
   const knit_z *vblk;
+  const knit_z *V;
+  int32_t onsite_dense;
+  int32_t reserved;
 } knit_strip;
 
 /*
@@ -107,7 +124,8 @@ typedef struct knit_strip {
  *   L           number of slices (>= 1)
  *   E           real energy
  *   onsite_off  offset, in knit_z elements, of its on-site blocks
- *               [L][W][norb][norb] in the `onsite` buffer
+ *               [L][W][norb][norb] (or [L][M][M] for an onsite_dense strip)
+ *               in the `onsite` buffer
  *   sigma_off   offset, in knit_z, of its Sigma_L / Sigma_R ([M][M]) in
  *               `sigmaL` / `sigmaR` (problems at the same energy and strip
  *               class may share one)
@@ -200,12 +218,16 @@ int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tunin
 int knit_sweep_tuning_get(int32_t precision, int32_t cls, knit_sweep_tuning *t);
 
 /*
- * Threshold of the KNIT_FP32_REFINE sweep (precision extension): after each
- * slice's FP32 inverse X0, the FP64 residual R = I - A_n X0 is formed; one
- * refinement step leaves a relative error of order |R|^2, so a problem whose
- * largest residual entry exceeds the threshold (or is NaN) is marked
- * KNIT_P_FALLBACK and recomputed in FP64.  Default 1e-3.  0 sends every
- * problem to FP64; +Inf never does.  Process-wide; returns KNIT_E_ARG for a
+ * Threshold of the KNIT_FP32_REFINE sweeps and LDOS (precision extension).
+ * Each slice's FP32 inverse X0 is refined by Newton steps on the inverse,
+ *   R_k = I - A_n X_k (FP64 product),  X_{k+1} = X_k + X_k R_k,
+ * each of which squares the residual; steps continue while ||R_k||_F > 1e-5
+ * (at most 4), so a refined inverse carries a relative error below about
+ * 1e-10.  A problem whose first residual ||I - A_n X0||_F exceeds the
+ * threshold (or is NaN), or whose steps stop shrinking the residual before
+ * reaching 1e-5, is marked KNIT_P_FALLBACK and recomputed in FP64.  Default
+ * 0.25 (Newton's iteration for the inverse converges for ||R_0|| < 1).  0
+ * sends every problem to FP64.  Process-wide; returns KNIT_E_ARG for a
  * negative or NaN value.
  */
 int knit_set_refine_threshold(double threshold);
@@ -265,7 +287,10 @@ int knit_transmission(const knit_strip *strips, int32_t n_strips, const knit_pro
  * then the reverse sweep
  *   G_LL = g_L,  G_nn = g_n + g_n V^+ G_{n+1,n+1} V g_n
  * recomputes each segment's g_n from its checkpoint.  checkpoint_stride <= 0
- * picks ceil(sqrt(L)).
+ * picks ceil(sqrt(L)).  precision as for knit_rgf_sweep (KNIT_FP32_REFINE:
+ * refined inverses, checkpoints, G_nn and both products in FP64, fallback
+ * problems recomputed in FP64 by the same call; M > 512 returns
+ * KNIT_E_UNSUPPORTED for it).
  *
  *   ldos   device output addressed by ldos_off ([L][M] doubles per problem)
  */
@@ -309,15 +334,20 @@ int knit_gamma_factor(int32_t M, const knit_z *sigma, int32_t n, double tol, kni
  * knit_gamma_factor for the left self-energy, addressed by sigma_off).  Only
  * the r = C_L's columns up to its last nonzero one enter, so each slice's
  * stacked elimination has Mp + r rows instead of 2 Mp (Mp = M rounded up to
- * 32).  Writes P_L to G1Np ([M][M] at out_off, rows >= r zero) and, if GNN is
- * not NULL, G_LL = g_L.  FP64 only; strips with M > 512 return
- * KNIT_E_UNSUPPORTED.  The workspace is knit_rgf_sweep_workspace(..., KNIT_FP64,
- * 0) bytes; other arguments as for knit_rgf_sweep.
+ * 32; with KNIT_FP32_REFINE the elimination covers A_n alone and P_n is the
+ * FP64 product (P_{n-1} V^+) g_n of the refined inverse).  Writes P_L to G1Np
+ * ([M][M] at out_off, rows >= r zero) and, if GNN is not NULL, G_LL = g_L.
+ * precision is KNIT_FP64, KNIT_FP32_REFINE (problems flagged KNIT_P_FALLBACK
+ * are recomputed in FP64 by a second launch of the same call) or KNIT_FP32;
+ * strips with M > 512 return KNIT_E_UNSUPPORTED.  The workspace is
+ * knit_rgf_sweep_workspace(..., precision, 0) bytes; other arguments as for
+ * knit_rgf_sweep.
  */
 int knit_rgf_sweep_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
                              const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
-                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
-                             knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream);
+                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, int32_t precision,
+                             knit_z *G1Np, knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes,
+                             void *stream);
 
 /*
  * Fisher-Lee transmission from the projected propagator (section 2.3, T_kl):
@@ -328,6 +358,32 @@ int knit_rgf_sweep_projected(const knit_strip *strips, int32_t n_strips, const k
 int knit_transmission_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
                                 const knit_problem *probs_dev, int32_t P, const knit_z *CR,
                                 const knit_z *G1Np, double *T, void *stream);
+
+/*
+ * Transmission eigenvalues and shot noise (section 2.1 item (a): conductance
+ * and shot noise), FP64, from the projected propagator.  With P_L = C_L^+ G_1L
+ * (knit_rgf_sweep_projected, G1Np at out_off) and Gamma_R = C_R C_R^+ (CR at
+ * sigma_off), t~ = P_L C_R has the singular values of the transmission
+ * amplitude matrix t = Gamma_R^{1/2} G_L1 Gamma_L^{1/2}; per problem:
+ *   tn[p * ld + i]  the transmission eigenvalues T_i (eigenvalues of t t^+),
+ *                   descending, i < nch[p] = min(rank Gamma_L, rank Gamma_R);
+ *                   entries nch[p] .. ld-1 are zero
+ *   T[p]            sum_i T_i = Tr t~^+ t~ (the Fisher-Lee T), or NULL
+ *   fano[p]         shot-noise Fano factor sum_i T_i (1 - T_i) / sum_i T_i,
+ *                   from traces (Tr tau - ||tau||_F^2) / Tr tau with
+ *                   tau = t~^+ t~; NaN where T = 0; or NULL
+ *   nch             device [P] int32, or NULL
+ * The eigenvalues come from a Householder reduction of tau to tridiagonal form
+ * and bisection on its Sturm sequence (absolute accuracy a few units of
+ * rounding of ||tau|| <= 1).  ld >= the largest M of the batch.  The workspace
+ * is knit_transmission_eigenvalues_workspace() bytes.
+ */
+size_t knit_transmission_eigenvalues_workspace(const knit_strip *strips, int32_t n_strips,
+                                               const knit_problem *probs_host, int32_t P);
+int knit_transmission_eigenvalues(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                  const knit_problem *probs_dev, int32_t P, const knit_z *CR, const knit_z *G1Np,
+                                  int32_t ld, double *tn, int32_t *nch, double *T, double *fano, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

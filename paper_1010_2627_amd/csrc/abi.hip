@@ -15,8 +15,27 @@ bool strip_ok(const knit_strip *s) {
   if (s->M < 1 || s->M > KNIT_MAX_M) return false;
   if (s->norb < 1 || s->norb > KNIT_MAX_NORB) return false;
   if (s->M % s->norb != 0) return false;
-  if (!s->H0 || !s->vcol || !s->vblk) return false;
+  if (!s->H0) return false;
+  if (!s->V && (!s->vcol || !s->vblk)) return false;
+  if (s->onsite_dense != 0 && s->onsite_dense != 1) return false;
   return true;
+}
+
+StripDev strip_dev(const knit_strip &s) {
+  return StripDev{s.M, s.norb, s.H0, s.vcol, s.vblk, s.V, s.onsite_dense};
+}
+
+// Dense couplings and dense on-site terms run on the matrix-core kernels only.
+bool generic_ok(const knit_strip *strips, int32_t n_strips) {
+  for (int i = 0; i < n_strips; ++i)
+    if (strips[i].V || strips[i].onsite_dense) return false;
+  return true;
+}
+
+bool any_dense_v(const knit_strip *strips, int32_t n_strips) {
+  for (int i = 0; i < n_strips; ++i)
+    if (strips[i].V) return true;
+  return false;
 }
 
 bool table_ok(const knit_strip *strips, int32_t n_strips) {
@@ -50,11 +69,28 @@ StripTable make_table(const knit_strip *strips, int32_t n) {
   StripTable t;
   memset(&t, 0, sizeof(t));
   t.n = n;
-  for (int i = 0; i < n; ++i) t.s[i] = StripDev{strips[i].M, strips[i].norb, strips[i].H0, strips[i].vcol, strips[i].vblk};
+  for (int i = 0; i < n; ++i) t.s[i] = strip_dev(strips[i]);
   return t;
 }
 
 bool precision_ok(int32_t p) { return p == KNIT_FP64 || p == KNIT_FP32_REFINE || p == KNIT_FP32; }
+
+}  // namespace
+
+namespace knit {
+
+bool batch_ok(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host, int32_t P,
+              int32_t precision, int *Mmax) {
+  int Lmax = 0;
+  return table_ok(strips, n_strips) && precision_ok(precision) &&
+         problems_ok(strips, n_strips, probs_host, P, Mmax, &Lmax);
+}
+
+StripTable strip_table_of(const knit_strip *strips, int32_t n) { return make_table(strips, n); }
+
+}  // namespace knit
+
+namespace {
 
 int resolve_stride(int stride, int Lmax) {
   if (stride > 0) return stride;
@@ -102,7 +138,7 @@ int knit_lead_selfenergy(const knit_strip *strip, int32_t side, const double *E,
   if (!E || !sigma || !pstatus) return KNIT_E_ARG;
   const size_t need = knit_lead_selfenergy_workspace(strip, nE);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
-  StripDev s{strip->M, strip->norb, strip->H0, strip->vcol, strip->vblk};
+  const StripDev s = strip_dev(*strip);
   hipError_t err = launch_decimation(s, side, E, nE, eta, tol, max_iter, sigma, iters, pstatus, ws,
                                      (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
@@ -116,8 +152,8 @@ size_t knit_rgf_sweep_workspace(const knit_strip *strips, int32_t n_strips,
   if (!table_ok(strips, n_strips) || !precision_ok(precision)) return 0;
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
   if (P == 0) return 0;
-  if (sweep_mfma_supports(Mmax)) return sweep_mfma_workspace(Mmax, precision, P);
-  if (precision == KNIT_FP32_REFINE) return 0;
+  if (sweep_mfma_supports(Mmax)) return sweep_mfma_workspace(Mmax, precision, P, any_dense_v(strips, n_strips));
+  if (precision == KNIT_FP32_REFINE || !generic_ok(strips, n_strips)) return 0;
   return sweep_slab_bytes(Mmax, precision) * (size_t)sweep_grid(P);
 }
 
@@ -132,14 +168,14 @@ int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_proble
   if (P == 0) return KNIT_OK;
   if (!probs_dev || !onsite || !sigmaL || !sigmaR || !G1N || !pstatus) return KNIT_E_ARG;
   const bool fast = sweep_mfma_supports(Mmax);
-  if (!fast && precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
+  if (!fast && (precision == KNIT_FP32_REFINE || !generic_ok(strips, n_strips))) return KNIT_E_UNSUPPORTED;
   const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, precision, GN1 != nullptr);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
   StripTable tab = make_table(strips, n_strips);
   hipError_t err;
   if (fast)
     err = launch_sweep_mfma(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN, pstatus, ws,
-                            Mmax, (hipStream_t)stream);
+                            Mmax, 0, (hipStream_t)stream);
   else
     err = launch_sweep(tab, probs_dev, P, onsite, sigmaL, sigmaR, precision, G1N, GN1, GNN, pstatus, ws,
                        sweep_slab_bytes(Mmax, precision), Mmax, (hipStream_t)stream);
@@ -191,7 +227,8 @@ size_t knit_ldos_workspace(const knit_strip *strips, int32_t n_strips,
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
   if (P == 0) return 0;
   const int st = resolve_stride(checkpoint_stride, Lmax);
-  if (sweep_mfma_supports(Mmax)) return ldos_mfma_workspace(Mmax, Lmax, st, precision, P);
+  if (sweep_mfma_supports(Mmax)) return ldos_mfma_workspace(Mmax, Lmax, st, precision, P, any_dense_v(strips, n_strips));
+  if (precision == KNIT_FP32_REFINE || !generic_ok(strips, n_strips)) return 0;
   const int grid = P < 1024 ? P : 1024;
   return ldos_slab_bytes(Mmax, Lmax, st, precision) * (size_t)grid;
 }
@@ -206,7 +243,8 @@ int knit_ldos(const knit_strip *strips, int32_t n_strips, const knit_problem *pr
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
   if (P == 0) return KNIT_OK;
   if (!probs_dev || !onsite || !sigmaL || !sigmaR || !ldos || !pstatus) return KNIT_E_ARG;
-  if (precision == KNIT_FP32_REFINE) return KNIT_E_UNSUPPORTED;
+  if (!sweep_mfma_supports(Mmax) && (precision == KNIT_FP32_REFINE || !generic_ok(strips, n_strips)))
+    return KNIT_E_UNSUPPORTED;
   const int st = resolve_stride(checkpoint_stride, Lmax);
   const size_t need = knit_ldos_workspace(strips, n_strips, probs_host, P, precision, checkpoint_stride);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
@@ -233,19 +271,19 @@ int knit_gamma_factor(int32_t M, const knit_z *sigma, int32_t n, double tol, kni
 
 int knit_rgf_sweep_projected(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
                              const knit_problem *probs_dev, int32_t P, const knit_z *onsite,
-                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
-                             knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
+                             const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, int32_t precision,
+                             knit_z *G1Np, knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
   int Mmax = 0, Lmax = 0;
-  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!table_ok(strips, n_strips) || !precision_ok(precision)) return KNIT_E_ARG;
   if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
   if (P == 0) return KNIT_OK;
   if (!probs_dev || !onsite || !sigmaL || !sigmaR || !CL || !G1Np || !pstatus) return KNIT_E_ARG;
   if (!sweep_mfma_supports(Mmax)) return KNIT_E_UNSUPPORTED;
-  const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, KNIT_FP64, 0);
+  const size_t need = knit_rgf_sweep_workspace(strips, n_strips, probs_host, P, precision, 0);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
   StripTable tab = make_table(strips, n_strips);
-  hipError_t err = launch_sweep_projected(tab, probs_dev, P, onsite, sigmaL, sigmaR, CL, G1Np, GNN, pstatus, ws,
-                                          Mmax, (hipStream_t)stream);
+  hipError_t err = launch_sweep_projected(tab, probs_dev, P, onsite, sigmaL, sigmaR, CL, precision, G1Np, GNN,
+                                          pstatus, ws, Mmax, 0, (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 
@@ -258,6 +296,32 @@ int knit_transmission_projected(const knit_strip *strips, int32_t n_strips, cons
   if (!probs_dev || !CR || !G1Np || !T) return KNIT_E_ARG;
   StripTable tab = make_table(strips, n_strips);
   hipError_t err = launch_transmission_proj(tab, probs_dev, P, CR, G1Np, T, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
+size_t knit_transmission_eigenvalues_workspace(const knit_strip *strips, int32_t n_strips,
+                                               const knit_problem *probs_host, int32_t P) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return 0;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
+  if (P == 0) return 0;
+  return transmission_eigs_workspace(Mmax, P);
+}
+
+int knit_transmission_eigenvalues(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                  const knit_problem *probs_dev, int32_t P, const knit_z *CR, const knit_z *G1Np,
+                                  int32_t ld, double *tn, int32_t *nch, double *T, double *fano, void *ws,
+                                  size_t ws_bytes, void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !CR || !G1Np || !tn || ld < Mmax) return KNIT_E_ARG;
+  const size_t need = knit_transmission_eigenvalues_workspace(strips, n_strips, probs_host, P);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_transmission_eigs(tab, probs_dev, P, Mmax, CR, G1Np, ld, tn, nch, T, fano, ws,
+                                            (hipStream_t)stream);
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 

@@ -27,12 +27,15 @@
 // Precision modes:
 //   FP64         elimination and state in FP64 (v_mfma_f64_16x16x4f64);
 //   FP32         elimination and state in FP32 (v_mfma_f32_16x16x4f32);
-//   FP32_REFINE  elimination in FP32; g_n and G_1n kept in FP64; per slice one
+//   FP32_REFINE  elimination of A_n alone in FP32 (X0 ~ A_n^{-1}); one
 //                refinement step on the inverse: R = I - A_n X0 with A_n and
-//                the product in FP64, then [g_n; G_1n] = [X0; G0] (I + R) with
-//                the correction product in FP32.  A slice whose largest |R|
-//                exceeds the refine threshold hands its problem to a second,
-//                FP64 pass of the same call (KNIT_P_FALLBACK).
+//                the product in FP64, g_n = X0 + X0 R (correction product in
+//                FP32, sum in FP64); the propagator is then an FP64 product
+//                of the refined inverse, G_1n = (G_{1,n-1} V^+) g_n (or
+//                P_n = (P_{n-1} V^+) g_n), so nothing the recursion carries
+//                from slice to slice is ever rounded to FP32.  A slice whose
+//                largest |R| exceeds the refine threshold hands its problem
+//                to a second, FP64 pass of the same call (KNIT_P_FALLBACK).
 //
 // The same machinery serves the batched FP64 inverse of the lead decimation
 // (inverse_fp64_kernel) and the LDOS backward sweep (ldos_mfma_kernel).
@@ -569,14 +572,15 @@ template <int no, class RG, bool REFINE, bool BOTTOM, class GAcc, class G1Acc>
 __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, StripDev s, int Mp,
                                                         double E, const knit_z *D, const knit_z *sL,
                                                         const knit_z *sR, bool first, bool last, GAcc gprev,
-                                                        G1Acc G1prev, int nbot) {
+                                                        G1Acc G1prev, int nbot, bool couple) {
   const int M = s.M, W = M / no, Wp = Mp / no;
   const int64_t E2 = (int64_t)Mp * Mp;
   // top: site blocks (sa, sb), one output row oa at a time
   for (int blk = threadIdx.x; blk < Wp * Wp; blk += blockDim.x) {
     const int sa = blk / Wp, sb = blk % Wp;
     const bool real = sa < W && sb < W;
-    const int ca = real ? s.vcol[sa] : -1, cb = real ? s.vcol[sb] : -1;
+    const bool cpl = couple && real;
+    const int ca = cpl ? s.vcol[sa] : -1, cb = cpl ? s.vcol[sb] : -1;
     const bool vgv = !first && ca >= 0 && cb >= 0;
     cpx<double> gb[no][no];
     if (vgv)
@@ -601,8 +605,8 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
         if (real) {
           const int64_t e = (int64_t)(sa * no + oa) * M + sb * no + ob;
           cpx<double> h = ld_z(s.H0 + e);
-          if (sa == sb) {
-            const cpx<double> d = ld_z(D + ((int64_t)sa * no + oa) * no + ob);
+          if (s.onsite_dense || sa == sb) {
+            const cpx<double> d = ld_z(D + (s.onsite_dense ? e : ((int64_t)sa * no + oa) * no + ob));
             h.re += d.re;
             h.im += d.im;
           }
@@ -633,7 +637,7 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
       }
     }
   }
-  if (first || !BOTTOM) return;
+  if (first || !BOTTOM || !couple) return;
   // bottom: row a, site block sb: -(G_{1,n-1} V^+)[a, sb]; rows a >= nbot (up to
   // the next multiple of MPAD) are zero
   const int Mb = (nbot + MPAD - 1) / MPAD * MPAD;
@@ -655,15 +659,69 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
   }
 }
 
+// couple = false leaves out the coupling terms (V g V^+ and the stacked rows):
+// with a dense V they are formed by dense_coupling afterwards.
 template <class RG, bool REFINE, bool BOTTOM = true, class GAcc, class G1Acc>
 __device__ void form_blocks(cpx<RG> *X, cpx<double> *A64, const StripDev &s, int Mp, double E,
                             const knit_z *D, const knit_z *sL, const knit_z *sR, bool first, bool last,
-                            GAcc gprev, G1Acc G1prev, int nbot = -1) {
+                            GAcc gprev, G1Acc G1prev, int nbot = -1, bool couple = true) {
   if (nbot < 0) nbot = s.M;
   switch (s.norb) {
-    case 1: form_blocks_n<1, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
-    case 2: form_blocks_n<2, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
-    default: form_blocks_n<4, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot); break;
+    case 1: form_blocks_n<1, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot, couple); break;
+    case 2: form_blocks_n<2, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot, couple); break;
+    default: form_blocks_n<4, RG, REFINE, BOTTOM>(X, A64, s, Mp, E, D, sL, sR, first, last, gprev, G1prev, nbot, couple); break;
+  }
+}
+
+// Dense inter-slice hopping V (general hopping matrices of Eq. (1)): the
+// coupling terms of the slice matrix as complex products on the matrix cores,
+// after form_blocks(couple = false) has written the rest:
+//   top:     A_n -= (V g_{n-1}) V^+              (two Mp^3 products, Tv scratch)
+//   stacked: X[Mp + r] = -(G_{1,n-1} V^+)[r]     for the first nbp rows
+// Vd = V and Vh = V^+ ([Mp][Mp], zero padded), g and G1 in natural order.
+// With REFINE the top is accumulated in FP64 in A64 and rounded into X.
+// Called by the whole workgroup; ends with a barrier.
+template <class RG, class RS, bool REFINE>
+__device__ __attribute__((noinline)) void dense_coupling(cpx<RG> *X, cpx<double> *A64, const cpx<RS> *Vd,
+                                                         const cpx<RS> *Vh, const cpx<RS> *g, const cpx<RS> *G1,
+                                                         cpx<RS> *Tv, int Mp, int nbp) {
+  const int64_t E2 = (int64_t)Mp * Mp;
+  wg_gemm_mfma<RS>(Mp, Mp, Mp, Vd, Mp, g, Mp, [&](int r, int c, RS &re, RS &im) {
+    Tv[(int64_t)r * Mp + c] = cpx<RS>{re, im};
+  });
+  __syncthreads();
+  wg_gemm_mfma<RS>(Mp, Mp, Mp, Tv, Mp, Vh, Mp, [&](int r, int c, RS &re, RS &im) {
+    const int64_t o = (int64_t)r * Mp + c;
+    if constexpr (REFINE) {
+      const cpx<double> a = {A64[o].re - (double)re, A64[o].im - (double)im};
+      A64[o] = a;
+      X[o] = cvt<RG>(a);
+    } else {
+      const cpx<RG> x = X[o];
+      X[o] = cpx<RG>{x.re - (RG)re, x.im - (RG)im};
+    }
+  });
+  if (nbp > 0)
+    wg_gemm_mfma<RS>(nbp, Mp, Mp, G1, Mp, Vh, Mp, [&](int r, int c, RS &re, RS &im) {
+      X[E2 + (int64_t)r * Mp + c] = cpx<RG>{(RG)-re, (RG)-im};
+    });
+  __syncthreads();
+}
+
+// Vd = V and Vh = V^+ of a dense-coupling strip, zero padded to [Mp][Mp].
+template <class RS>
+__device__ void load_dense_v(cpx<RS> *Vd, cpx<RS> *Vh, const StripDev &s, int Mp) {
+  const int M = s.M;
+  for (int64_t i = threadIdx.x; i < (int64_t)Mp * Mp; i += blockDim.x) {
+    const int a = (int)(i / Mp), b = (int)(i % Mp);
+    cpx<double> v = {0.0, 0.0}, vt = {0.0, 0.0};
+    if (a < M && b < M) {
+      v = ld_z(s.V + (int64_t)a * M + b);
+      const cpx<double> w = ld_z(s.V + (int64_t)b * M + a);
+      vt = {w.re, -w.im};
+    }
+    Vd[i] = cvt<RS>(v);
+    Vh[i] = cvt<RS>(vt);
   }
 }
 
@@ -685,11 +743,12 @@ __device__ void gather_vg(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int 
   }
 }
 
-// Y = Gm V^+ (columns of Gm gathered through vcol), padded columns zero
+// Y = Gm V^+ (columns of Gm gathered through vcol) on the first `nrows` rows
+// (default all Mp), padded rows and columns zero
 template <class RS>
-__device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int Mp) {
+__device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int Mp, int nrows = -1) {
   const int M = s.M, no = s.norb;
-  const int64_t E2 = (int64_t)Mp * Mp;
+  const int64_t E2 = (int64_t)(nrows < 0 ? Mp : nrows) * Mp;
   for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) {
     const int a = (int)(i / Mp), b = (int)(i % Mp);
     cpx<double> acc = {0.0, 0.0};
@@ -701,6 +760,120 @@ __device__ void gather_gvdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, i
     }
     Y[i] = cvt<RS>(acc);
   }
+}
+
+// Workgroup sum of a non-negative double, NaN if any thread holds NaN.  sv: one
+// slot per wave; ends with a barrier, so sv is free again on return.
+__device__ __forceinline__ double wg_sum_nan(double v, double *sv) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sv[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sv[w];
+  __syncthreads();
+  return r;
+}
+
+// Refined inverse of a slice (precision extension), called by the whole
+// workgroup after the FP32 elimination of A_n.  X0 (the elimination result X
+// through the row map q and column map pinv) goes to Xn in natural order;
+// then Newton steps on the inverse,
+//   R_k = I - A_n X_k  (FP64 product, A_n and X_k exact in FP64),
+//   X_{k+1} = X_k + X_k R_k  (correction product in FP32, sum in FP64),
+// each of which squares the residual: ||I - A_n X_{k+1}|| <= ||R_k||^2 plus
+// the FP32 rounding of the correction (about 6e-8 ||R_k|| relative).  Steps
+// continue while ||R_k||_F > REFINE_TARGET (at most REFINE_MAX_STEPS), so a
+// refined inverse carries a relative error below about REFINE_TARGET^2.  g
+// receives X_final in FP64.  Returns the number of steps, or 0 (g undefined)
+// when ||R_0||_F exceeds tol or is NaN, or when the steps stop shrinking the
+// residual above the target: the problem then goes to the FP64 pass.  Rr holds
+// R_k in FP32 (only its leading digits enter the correction).  Out of line:
+// shared by the sweep and the LDOS kernels.
+constexpr double REFINE_TARGET = 1e-5;
+constexpr int REFINE_MAX_STEPS = 4;
+template <class RS>
+__device__ __attribute__((noinline)) int refine_inverse(const cpx<float> *X, const int *q, const int *pinv, int Mp,
+                                                        const cpx<double> *A64, cpx<float> *Xn, cpx<float> *Rr,
+                                                        cpx<RS> *g, double tol, double *sv) {
+  const int64_t E2 = (int64_t)Mp * Mp;
+  for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) {
+    const int a = (int)(i / Mp), b = (int)(i % Mp);
+    Xn[i] = X[(int64_t)q[a] * Mp + pinv[b]];
+  }
+  __syncthreads();
+  double fprev = 0.0;
+  for (int k = 0; k < REFINE_MAX_STEPS; ++k) {
+    // residual of the current inverse (X0 in FP32 at k = 0, g in FP64 after)
+    double ss = 0.0;
+    auto resid = [&](int r, int c, double &re, double &im) {
+      const double rr = (r == c ? 1.0 : 0.0) - re, ri = -im;
+      ss += rr * rr + ri * ri;
+      Rr[(int64_t)r * Mp + c] = cpx<float>{(float)rr, (float)ri};
+    };
+    if (k == 0) wg_gemm_mfma<double>(Mp, Mp, Mp, A64, Mp, Xn, Mp, resid);
+    else wg_gemm_mfma<double>(Mp, Mp, Mp, A64, Mp, g, Mp, resid);
+    const double f = sqrt(wg_sum_nan(ss, sv));
+    if (k == 0 ? !(f <= tol) : !(f < fprev)) return 0;
+    if (k > 0) {
+      // the FP32 operand of the correction
+      for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) Xn[i] = cvt<float>(g[i]);
+      __syncthreads();
+    }
+    // X_{k+1} = X_k + X_k R_k; every element of g is read and written by the
+    // lane that owns it in the epilogue only
+    wg_gemm_mfma<float>(Mp, Mp, Mp, Xn, Mp, Rr, Mp, [&](int r, int c, float &re, float &im) {
+      const int64_t o = (int64_t)r * Mp + c;
+      const cpx<double> x = k == 0 ? cvt<double>(Xn[o]) : cvt<double>(g[o]);
+      g[o] = cvt<RS>(cpx<double>{x.re + (double)re, x.im + (double)im});
+    });
+    __syncthreads();
+    if (f <= REFINE_TARGET) return k + 1;
+    fprev = f;
+  }
+  return 0;
+}
+
+// Propagator of the refined sweep as an FP64 product of the refined inverse g
+// (natural order), in place in G1:
+//   slice 1 (n == 0): G_11 = g_1, or P_1 = C_L^+ g_1 with CLp = C_L (rows >= rl zero)
+//   later:            G_1n = (G_{1,n-1} V^+) g_n, or P_n = (P_{n-1} V^+) g_n
+// on the first nb rows (Mp, or the projected rows rounded up to 32).  Tb is
+// [nb][Mp] scratch; Vh = V^+ for a dense V (else V is gathered through vcol).
+template <class RS>
+__device__ __attribute__((noinline)) void refined_propagator(cpx<RS> *G1, cpx<RS> *Tb, const cpx<RS> *g,
+                                                             StripDev s, int Mp, int n, const knit_z *CLp, int rl,
+                                                             int nb, const cpx<RS> *Vh) {
+  const int64_t E2 = (int64_t)Mp * Mp;
+  const int M = s.M;
+  if (n == 0 && !CLp) {
+    for (int64_t i = threadIdx.x; i < E2; i += blockDim.x) G1[i] = g[i];
+    __syncthreads();
+    return;
+  }
+  if (n == 0) {
+    for (int64_t i = threadIdx.x; i < (int64_t)nb * Mp; i += blockDim.x) {
+      const int a = (int)(i / Mp), b = (int)(i % Mp);
+      cpx<double> v = {0.0, 0.0};
+      if (a < rl && b < M) {
+        const cpx<double> c = ld_z(CLp + (int64_t)b * M + a);
+        v = {c.re, -c.im};
+      }
+      Tb[i] = cvt<RS>(v);
+    }
+  } else if (Vh) {
+    // dense V: G_{1,n-1} V^+ as a product
+    wg_gemm_mfma<double>(nb, Mp, Mp, G1, Mp, Vh, Mp, [&](int r, int c, double &re, double &im) {
+      Tb[(int64_t)r * Mp + c] = cvt<RS>(cpx<double>{re, im});
+    });
+  } else {
+    gather_gvdag<RS>(Tb, G1, s, Mp, nb);
+  }
+  __syncthreads();
+  wg_gemm_mfma<double>(nb, Mp, Mp, Tb, Mp, g, Mp, [&](int r, int c, double &re, double &im) {
+    G1[(int64_t)r * Mp + c] = cvt<RS>(cpx<double>{re, im});
+  });
+  __syncthreads();
 }
 
 // Queue order for the persistent sweep.  policy 0: problem order.  policy 1:
@@ -777,17 +950,24 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t EE = (int64_t)Mpmax * Mpmax;
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
-  cpx<RG> *Xa = reinterpret_cast<cpx<RG> *>(slab);                // [2 Mp][Mp]
-  cpx<RG> *Xb = Xa + 2 * EE;                                       // [2 Mp][Mp]
-  cpx<RS> *g = reinterpret_cast<cpx<RS> *>(Xb + 2 * EE);          // [Mp][Mp]  natural order (refine / G_n1)
+  // the refined sweep eliminates A_n alone: its elimination buffers hold Mp rows
+  constexpr int XROWS = REFINE ? 1 : 2;
+  cpx<RG> *Xa = reinterpret_cast<cpx<RG> *>(slab);                // [2 Mp][Mp]  ([Mp][Mp] refined)
+  cpx<RG> *Xb = Xa + XROWS * EE;                                   // [2 Mp][Mp]  ([Mp][Mp] refined)
+  cpx<RS> *g = reinterpret_cast<cpx<RS> *>(Xb + XROWS * EE);      // [Mp][Mp]  natural order (refine / G_n1)
   cpx<RS> *G1 = g + EE;                                           // [Mp][Mp]
   cpx<RS> *N1a = G1 + EE;                                         // [Mp][Mp]
   cpx<RS> *N1b = N1a + EE;                                        // [Mp][Mp]
   cpx<double> *A64 = reinterpret_cast<cpx<double> *>(N1b + EE);   // [Mp][Mp]   (REFINE)
-  cpx<float> *Xn = reinterpret_cast<cpx<float> *>(A64 + (REFINE ? EE : 0));   // [2 Mp][Mp] (REFINE)
-  cpx<float> *Rr = Xn + (REFINE ? 2 * EE : 0);                    // [Mp][Mp]   (REFINE)
+  cpx<RS> *Tb = reinterpret_cast<cpx<RS> *>(A64 + (REFINE ? EE : 0));   // [Mp][Mp] (REFINE) G_{1,n-1} V^+
+  cpx<float> *Xn = reinterpret_cast<cpx<float> *>(Tb + (REFINE ? EE : 0));    // [Mp][Mp] (REFINE)
+  cpx<float> *Rr = Xn + (REFINE ? EE : 0);                        // [Mp][Mp]   (REFINE)
   cpx<RG> *Sb = reinterpret_cast<cpx<RG> *>(Rr + (REFINE ? EE : 0));   // [2 Mp][NO] scratch
   cpx<RG> *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;                       // [NO][Mp]   scratch
+  // dense V (present in the slab only when the batch has a dense-coupling strip)
+  cpx<RS> *Vd = reinterpret_cast<cpx<RS> *>(Sd + (int64_t)NO_MAX * Mpmax);   // [Mp][Mp] V
+  cpx<RS> *Vh = Vd + EE;                                                      // [Mp][Mp] V^+
+  cpx<RS> *Tv = Vh + EE;                                                      // [Mp][Mp] V g
   const bool want_n1 = GN1 != nullptr;
   const double qnan = __builtin_nan("");
 
@@ -813,15 +993,25 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
     const int rl = PROJ ? rows[p] : 0;
     const int rlp = (rl + MPAD - 1) / MPAD * MPAD;
     const int nbot = PROJ ? rl : M;
+    // dense V: coupling terms as matrix-core products of natural-order g and G_1n
+    const bool dense = s.V != nullptr;
+    if (dense) {
+      load_dense_v<RS>(Vd, Vh, s, Mp);
+      __syncthreads();
+    }
     int flags = 0;
     int *q = qa, *pinv = pa, *qp = qb, *pinvp = pb;
     cpx<RG> *X = Xa, *Xp = Xb;
     for (int n = 0; n < L; ++n) {
-      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * M * no;
-      if (REFINE || n == 0) {
-        form_blocks<RG, REFINE>(X, A64, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * s.onsite_stride();
+      if (REFINE || n == 0 || dense) {
+        form_blocks<RG, REFINE, !REFINE>(X, A64, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
                                 [=](int r, int c) { return cvt<double>(g[(int64_t)r * Mp + c]); },
-                                [=](int r, int c) { return cvt<double>(G1[(int64_t)r * Mp + c]); });
+                                [=](int r, int c) { return cvt<double>(G1[(int64_t)r * Mp + c]); }, -1, !dense);
+        if (dense && n > 0) {
+          __syncthreads();
+          dense_coupling<RG, RS, REFINE>(X, A64, Vd, Vh, g, G1, Tv, Mp, REFINE ? 0 : (PROJ ? rlp : Mp));
+        }
       } else {
         // previous result in Xp: logical row r at physical row qp[r], column c of the
         // inverse at column pinvp[c]; G_11 = g_1 is the top of slice 1's result
@@ -835,7 +1025,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
                                },
                                nbot);
       }
-      if (PROJ && n == 0) {
+      if (PROJ && !REFINE && n == 0) {
         // bottom block of slice 1: -C_L^+ (rows >= rl zero)
         for (int64_t i = tid; i < (int64_t)rlp * Mp; i += nt) {
           const int a = (int)(i / Mp), b = (int)(i % Mp);
@@ -848,47 +1038,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
         }
       }
       __syncthreads();
-      const int R = PROJ ? Mp + rlp : (n > 0 ? 2 * Mp : Mp);
+      const int R = REFINE ? Mp : (PROJ ? Mp + rlp : (n > 0 ? 2 * Mp : Mp));
       flags |= outer == 128 ? gj_two_level<RG, NT, 128>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd)
                             : gj_two_level<RG, NT, 64>(X, Mp, R, q, xchg, prow, sv, si, Sb, Sd);
       for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
       __syncthreads();
       // logical row a of the result sits in physical row q[a] (a < Mp)
-      if (REFINE) {
-        // X0 (and G0) in natural column order
-        for (int64_t i = tid; i < (int64_t)R * Mp; i += nt) {
-          const int a = (int)(i / Mp), b = (int)(i % Mp);
-          Xn[i] = cvt<float>(X[(int64_t)(a < Mp ? q[a] : a) * Mp + pinv[b]]);
-        }
-        __syncthreads();
-        // residual R = I - A_n X0, FP64 product, and its largest entry
-        double rmax = 0.0;
-        wg_gemm_mfma<double>(Mp, Mp, Mp, A64, Mp, Xn, Mp, [&](int r, int c, double &re, double &im) {
-          const double rr = (r == c ? 1.0 : 0.0) - re, ri = -im;
-          const double a = fabs(rr) + fabs(ri);
-          rmax = (a != a || rmax != rmax) ? __builtin_nan("") : fmax(rmax, a);
-          Rr[(int64_t)r * Mp + c] = cpx<float>{(float)rr, (float)ri};
-        });
-        rmax = wg_max_nan(rmax, sv);
-        // one step leaves a relative error ~ |R|^2: beyond the threshold (or on a
-        // diverging inverse) the problem is handed to the FP64 pass
-        if (!(rmax <= refine_tol)) {
+      if constexpr (REFINE) {
+        // one FP64-residual step on the FP32 inverse, then the propagator as an
+        // FP64 product of the refined inverse; a slice too poor for one step
+        // hands the problem to the FP64 pass
+        if (refine_inverse<RS>(X, q, pinv, Mp, A64, Xn, Rr, g, refine_tol, sv) == 0) {
           flags |= KNIT_P_FALLBACK;
           break;
         }
-        // [g; G1] = [X0; G0] + [X0; G0] R, correction in FP32
-        wg_gemm_mfma<float>(R, Mp, Mp, Xn, Mp, Rr, Mp, [&](int r, int c, float &re, float &im) {
-          const int64_t o = (int64_t)r * Mp + c;
-          cpx<double> v = {(double)Xn[o].re + (double)re, (double)Xn[o].im + (double)im};
-          if (r < Mp) g[o] = cvt<RS>(v);
-          else G1[o - E2] = cvt<RS>(v);
-        });
-        __syncthreads();
-        if (n == 0) {
-          for (int64_t i = tid; i < E2; i += nt) G1[i] = g[i];
-          __syncthreads();
-        }
-      } else if (want_n1 || n == L - 1) {
+        refined_propagator<RS>(G1, Tb, g, s, Mp, n, PROJ ? CL + pr.sigma_off : nullptr, rl, PROJ ? rlp : Mp,
+                               dense ? Vh : nullptr);
+      } else if (want_n1 || n == L - 1 || dense) {
         // natural-order g_n (and G_1n) when G_n1 is carried, and for the outputs
         for (int64_t i = tid; i < (int64_t)R * Mp; i += nt) {
           const int a = (int)(i / Mp), b = (int)(i % Mp);
@@ -906,7 +1072,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) sw
         if (n == 0) {
           for (int64_t i = tid; i < E2; i += nt) N1a[i] = g[i];
         } else {
-          gather_vg<RS>(N1b, N1a, s, Mp);
+          if (dense)
+            wg_gemm_mfma<RS>(Mp, Mp, Mp, Vd, Mp, N1a, Mp, [&](int r, int c, RS &re, RS &im) {
+              N1b[(int64_t)r * Mp + c] = cpx<RS>{re, im};
+            });
+          else
+            gather_vg<RS>(N1b, N1a, s, Mp);
           __syncthreads();
           wg_gemm_mfma<RS>(Mp, Mp, Mp, g, Mp, N1b, Mp, [&](int r, int c, RS &re, RS &im) {
             N1a[(int64_t)r * Mp + c] = cpx<RS>{re, im};
@@ -996,14 +1167,22 @@ inverse_fp64_kernel(cpx<double> *X, int64_t xstride, cpx<double> *scratch, int64
 //   reverse:  per segment, g_n recomputed from its checkpoint, then
 //             G_LL = g_L,  G_nn = g_n + (g_n V^+) G_{n+1,n+1} (V g_n)
 //             with the two products on MFMA;  LDOS_n[i] = -Im (G_nn)_ii / pi.
-// Slab (Mp^2 elements each): X, Gnn, U, W, T, the segment's g [max(st, 2)],
-// checkpoints [ceil(Lmax / st)], then the elimination scratch.
-template <class RG, int NT>
+// RG is the elimination type, RS the type of everything kept (g_n, the
+// checkpoints, G_nn and the products).  REFINE (RG float, RS double): each
+// g_n is the FP32 inverse X0 plus one FP64-residual step, X0 + X0 (I - A_n X0),
+// as in the refined sweep, and a slice whose residual exceeds the refine
+// threshold hands the problem to a second, FP64 pass (KNIT_P_FALLBACK).
+// Slab (Mp^2 elements each): X (RG), Gnn, U, W, T (RS), the segment's g
+// [max(st, 2)], checkpoints [ceil(Lmax / st)] (RS), with REFINE A_n (FP64),
+// X0 and R (FP32), then the elimination scratch (RG).
+template <class RG, class RS, bool REFINE, int NT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z *onsite, const knit_z *sigmaL,
                  const knit_z *sigmaR, int stride, double *ldos, int32_t *pstatus, char *ws, size_t slab_bytes,
-                 int Mpmax, int Lmax, unsigned int *queue, const int *order, int outer) {
+                 int Mpmax, int Lmax, unsigned int *queue, const int *order, int outer, double refine_tol,
+                 const int32_t *redo) {
   using C = cpx<RG>;
+  using S = cpx<RS>;
   __shared__ int next_p;
   __shared__ int q[NT], pinv[NT];
   __shared__ double sv[32];
@@ -1016,11 +1195,17 @@ ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z 
   const int nsegmax = (Lmax + stride - 1) / stride;
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
   C *X = reinterpret_cast<C *>(slab);
-  C *Gnn = X + EE, *U = Gnn + EE, *W = U + EE, *T1 = W + EE;
-  C *seg = T1 + EE;                              // [segbuf][Mp][Mp]
-  C *cps = seg + (int64_t)segbuf * EE;           // [nsegmax][Mp][Mp]
-  C *Sb = cps + (int64_t)nsegmax * EE;           // [2 Mp][NO] scratch
-  C *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;      // [NO][Mp]   scratch
+  S *Gnn = reinterpret_cast<S *>(X + EE), *U = Gnn + EE, *W = U + EE, *T1 = W + EE;
+  S *seg = T1 + EE;                              // [segbuf][Mp][Mp]
+  S *cps = seg + (int64_t)segbuf * EE;           // [nsegmax][Mp][Mp]
+  cpx<double> *A64 = reinterpret_cast<cpx<double> *>(cps + (int64_t)nsegmax * EE);   // (REFINE)
+  cpx<float> *Xn = reinterpret_cast<cpx<float> *>(A64 + (REFINE ? EE : 0));           // (REFINE)
+  cpx<float> *Rr = Xn + (REFINE ? EE : 0);                                             // (REFINE)
+  C *Sb = reinterpret_cast<C *>(Rr + (REFINE ? EE : 0));   // [2 Mp][NO] scratch
+  C *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;                // [NO][Mp]   scratch
+  // dense V (present in the slab only when the batch has a dense-coupling strip)
+  S *Vd = reinterpret_cast<S *>(Sd + (int64_t)NO_MAX * Mpmax);   // [Mp][Mp] V
+  S *Vh = Vd + EE;                                               // [Mp][Mp] V^+
   const double qnan = __builtin_nan("");
   const double inv_pi = 0.318309886183790671537767526745;
   for (;;) {
@@ -1030,6 +1215,8 @@ ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z 
     __syncthreads();
     if (pi >= P) break;
     const int p = order[pi];
+    // second pass of a refined call: only the problems the first pass gave up on
+    if (redo && !(redo[p] & KNIT_P_FALLBACK)) continue;
     const knit_problem pr = probs[p];
     const StripDev s = tab.s[pr.strip];
     const int M = s.M, no = s.norb, L = pr.L;
@@ -1037,62 +1224,85 @@ ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z 
     const int64_t E2 = (int64_t)Mp * Mp;
     const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
     const int nseg = (L + stride - 1) / stride;
-    int flags = 0;
-    // g_n (natural order, into dst) from g_{n-1} (natural order, or none for n = 0)
-    auto step = [&](int n, const C *gprev, C *dst) {
-      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * M * no;
-      form_blocks<RG, false, false>(X, nullptr, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
-                                    [=](int r, int c) { return cvt<double>(gprev[(int64_t)r * Mp + c]); },
-                                    [=](int r, int c) { return cpx<double>{0.0, 0.0}; });
+    const bool dense = s.V != nullptr;
+    if (dense) {
+      load_dense_v<RS>(Vd, Vh, s, Mp);
       __syncthreads();
+    }
+    int flags = 0;
+    // g_n (natural order, into dst) from g_{n-1} (natural order, or none for n = 0);
+    // false when a refined slice is too poor for one step (uniform over the workgroup)
+    auto step = [&](int n, const S *gprev, S *dst) -> bool {
+      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * s.onsite_stride();
+      form_blocks<RG, REFINE, false>(X, A64, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+                                     [=](int r, int c) { return cvt<double>(gprev[(int64_t)r * Mp + c]); },
+                                     [=](int r, int c) { return cpx<double>{0.0, 0.0}; }, -1, !dense);
+      __syncthreads();
+      // dense V: A_n -= (V g_{n-1}) V^+ on the matrix cores (T1 is free here)
+      if (dense && n > 0) dense_coupling<RG, RS, REFINE>(X, A64, Vd, Vh, gprev, nullptr, T1, Mp, 0);
       flags |= outer == 128 ? gj_two_level<RG, NT, 128>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
                             : gj_two_level<RG, NT, 64>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
       for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
       __syncthreads();
-      for (int64_t i = tid; i < E2; i += nt) {
-        const int a = (int)(i / Mp), b = (int)(i % Mp);
-        dst[i] = X[(int64_t)q[a] * Mp + pinv[b]];
+      if constexpr (REFINE) {
+        if (refine_inverse<RS>(X, q, pinv, Mp, A64, Xn, Rr, dst, refine_tol, sv) == 0) return false;
+      } else {
+        for (int64_t i = tid; i < E2; i += nt) {
+          const int a = (int)(i / Mp), b = (int)(i % Mp);
+          dst[i] = cvt<RS>(X[(int64_t)q[a] * Mp + pinv[b]]);
+        }
       }
       __syncthreads();
+      return true;
     };
+    bool ok = true;
     // forward pass: checkpoint k holds g_{k st - 1} (k >= 1)
     {
-      C *cur = seg, *prev = seg + E2;
-      for (int n = 0; n < L; ++n) {
-        step(n, prev, cur);
-        if ((n + 1) % stride == 0 && n + 1 < L) {
-          C *cp = cps + (int64_t)((n + 1) / stride) * E2;
+      S *cur = seg, *prev = seg + E2;
+      for (int n = 0; n < L && ok; ++n) {
+        ok = step(n, prev, cur);
+        if (ok && (n + 1) % stride == 0 && n + 1 < L) {
+          S *cp = cps + (int64_t)((n + 1) / stride) * E2;
           for (int64_t i = tid; i < E2; i += nt) cp[i] = cur[i];
           __syncthreads();
         }
-        C *t = cur;
+        S *t = cur;
         cur = prev;
         prev = t;
       }
     }
     // reverse pass, one segment at a time
     double *out = ldos + pr.ldos_off;
-    for (int k = nseg - 1; k >= 0; --k) {
+    for (int k = nseg - 1; k >= 0 && ok; --k) {
       const int n0 = k * stride, n1 = min(L, n0 + stride);
-      for (int n = n0; n < n1; ++n) {
-        const C *gprev = n == n0 ? (k > 0 ? cps + (int64_t)k * E2 : seg) : seg + (int64_t)(n - n0 - 1) * E2;
-        step(n, gprev, seg + (int64_t)(n - n0) * E2);
+      for (int n = n0; n < n1 && ok; ++n) {
+        const S *gprev = n == n0 ? (k > 0 ? cps + (int64_t)k * E2 : seg) : seg + (int64_t)(n - n0 - 1) * E2;
+        ok = step(n, gprev, seg + (int64_t)(n - n0) * E2);
       }
-      for (int n = n1 - 1; n >= n0; --n) {
-        const C *g = seg + (int64_t)(n - n0) * E2;
+      for (int n = n1 - 1; n >= n0 && ok; --n) {
+        const S *g = seg + (int64_t)(n - n0) * E2;
         if (n == L - 1) {
           for (int64_t i = tid; i < E2; i += nt) Gnn[i] = g[i];
         } else {
-          gather_gvdag<RG>(U, g, s, Mp);     // g V^+
-          gather_vg<RG>(W, g, s, Mp);        // V g
+          if (dense) {
+            wg_gemm_mfma<RS>(Mp, Mp, Mp, g, Mp, Vh, Mp, [&](int r, int c, RS &re, RS &im) {
+              U[(int64_t)r * Mp + c] = S{re, im};      // g V^+
+            });
+            wg_gemm_mfma<RS>(Mp, Mp, Mp, Vd, Mp, g, Mp, [&](int r, int c, RS &re, RS &im) {
+              W[(int64_t)r * Mp + c] = S{re, im};      // V g
+            });
+          } else {
+            gather_gvdag<RS>(U, g, s, Mp);     // g V^+
+            gather_vg<RS>(W, g, s, Mp);        // V g
+          }
           __syncthreads();
-          wg_gemm_mfma<RG>(Mp, Mp, Mp, U, Mp, Gnn, Mp, [&](int r, int c, RG &re, RG &im) {
-            T1[(int64_t)r * Mp + c] = C{re, im};
+          wg_gemm_mfma<RS>(Mp, Mp, Mp, U, Mp, Gnn, Mp, [&](int r, int c, RS &re, RS &im) {
+            T1[(int64_t)r * Mp + c] = S{re, im};
           });
           __syncthreads();
-          wg_gemm_mfma<RG>(Mp, Mp, Mp, T1, Mp, W, Mp, [&](int r, int c, RG &re, RG &im) {
+          wg_gemm_mfma<RS>(Mp, Mp, Mp, T1, Mp, W, Mp, [&](int r, int c, RS &re, RS &im) {
             const int64_t o = (int64_t)r * Mp + c;
-            Gnn[o] = C{g[o].re + re, g[o].im + im};
+            Gnn[o] = S{g[o].re + re, g[o].im + im};
           });
         }
         __syncthreads();
@@ -1100,14 +1310,20 @@ ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z 
         __syncthreads();
       }
     }
-    // non-finite check over the outputs
-    double bad = 0.0;
-    for (int64_t i = tid; i < (int64_t)L * M; i += nt) bad = fmax(bad, fabs(out[i]));
-    if (bad != bad) bad = INFINITY;
-    bad = wg_max_nan(bad, sv);
-    if (!(bad <= 1.79e308)) flags |= KNIT_P_NONFINITE;
-    if (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE))
-      for (int64_t i = tid; i < (int64_t)L * M; i += nt) out[i] = qnan;
+    if (!ok) flags |= KNIT_P_FALLBACK;
+    // a problem the refined pass gave up on only records that; the FP64 pass
+    // writes its outputs
+    if (redo) flags |= KNIT_P_FALLBACK;
+    if (redo || ok) {
+      // non-finite check over the outputs
+      double bad = 0.0;
+      for (int64_t i = tid; i < (int64_t)L * M; i += nt) bad = fmax(bad, fabs(out[i]));
+      if (bad != bad) bad = INFINITY;
+      bad = wg_max_nan(bad, sv);
+      if (!(bad <= 1.79e308)) flags |= KNIT_P_NONFINITE;
+      if (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE))
+        for (int64_t i = tid; i < (int64_t)L * M; i += nt) out[i] = qnan;
+    }
     if (tid == 0) pstatus[p] = flags;
     __syncthreads();
   }
@@ -1119,33 +1335,54 @@ int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
 
 static size_t order_bytes(int P) { return (((size_t)P * sizeof(int)) + 255) & ~size_t(255); }
 
-size_t sweep_mfma_slab_bytes(int Mmax, int precision) {
+size_t sweep_mfma_slab_bytes(int Mmax, int precision, bool dense) {
   const size_t Mp = (size_t)mfma_padded(Mmax);
   const size_t EE = Mp * Mp;
   const size_t gs = precision == KNIT_FP64 ? 16 : 8;     // elimination element size
-  size_t b;
-  if (precision == KNIT_FP64) b = EE * (4 * 16 + 4 * 16);
-  else if (precision == KNIT_FP32) b = EE * (4 * 8 + 4 * 8);
-  else b = EE * (4 * 8 + 4 * 16 + 16 + 2 * 8 + 8);
+  const size_t ss = precision == KNIT_FP32 ? 8 : 16;     // kept state element size
+  size_t b = dense ? 3 * EE * ss : 0;                    // V, V^+, V g
+
+  if (precision == KNIT_FP64) b += EE * (4 * 16 + 4 * 16);
+  else if (precision == KNIT_FP32) b += EE * (4 * 8 + 4 * 8);
+  else b += EE * (2 * 8 + 4 * 16 + 16 + 16 + 8 + 8);   // Xa, Xb (Mp rows); g, G1, N1a, N1b; A64; Tb; Xn; Rr
   b += (2 * Mp * NO_MAX + NO_MAX * Mp) * gs;              // Sb, Sd scratch
   return (b + 255) & ~size_t(255);
 }
 
 bool sweep_mfma_supports(int Mmax) { return mfma_padded(Mmax) <= 512; }
 
-size_t ldos_mfma_slab_bytes(int Mmax, int Lmax, int stride, int precision) {
+size_t ldos_mfma_slab_bytes(int Mmax, int Lmax, int stride, int precision, bool dense) {
   const size_t Mp = (size_t)mfma_padded(Mmax);
   const size_t EE = Mp * Mp;
-  const size_t cs = precision == KNIT_FP64 ? 16 : 8;
+  const size_t gs = precision == KNIT_FP64 ? 16 : 8;                   // elimination element
+  const size_t ss = precision == KNIT_FP32 ? 8 : 16;                   // kept state element
   const size_t segbuf = stride < 2 ? 2 : stride;
   const size_t nseg = (Lmax + stride - 1) / stride;
-  size_t b = (5 + segbuf + nseg) * EE * cs + (2 * Mp * NO_MAX + NO_MAX * Mp) * cs;
+  size_t b = EE * gs + (4 + segbuf + nseg) * EE * ss + (2 * Mp * NO_MAX + NO_MAX * Mp) * gs;
+  if (precision == KNIT_FP32_REFINE) b += EE * (16 + 8 + 8);            // A_n, X0, R
+  if (dense) b += 2 * EE * ss;                                          // V, V^+
   return (b + 255) & ~size_t(255);
 }
 
-size_t ldos_mfma_workspace(int Mmax, int Lmax, int stride, int precision, int P) {
+// The refined call's second (FP64) pass shares the workspace.
+static size_t ldos_slab_for(int Mmax, int Lmax, int stride, int precision, bool dense) {
+  size_t s = ldos_mfma_slab_bytes(Mmax, Lmax, stride, precision, dense);
+  if (precision == KNIT_FP32_REFINE) {
+    const size_t s64 = ldos_mfma_slab_bytes(Mmax, Lmax, stride, KNIT_FP64, dense);
+    if (s64 > s) s = s64;
+  }
+  return s;
+}
+
+size_t ldos_mfma_workspace(int Mmax, int Lmax, int stride, int precision, int P, bool dense) {
   const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
-  return 256 + order_bytes(P) + ldos_mfma_slab_bytes(Mmax, Lmax, stride, precision) * (size_t)grid;
+  return 256 + order_bytes(P) + ldos_slab_for(Mmax, Lmax, stride, precision, dense) * (size_t)grid;
+}
+
+bool table_has_dense(const StripTable &tab) {
+  for (int i = 0; i < tab.n; ++i)
+    if (tab.s[i].V) return true;
+  return false;
 }
 
 hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
@@ -1160,28 +1397,39 @@ hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, in
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  const knit_sweep_tuning tune = sweep_tuning_get(precision, Mpmax);
-  const size_t slab = ldos_mfma_slab_bytes(Mmax, Lmax, stride, precision);
-  int grid = tune.wg_per_cu * ncu;
-  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
-  if (grid > P) grid = P;
-  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr, order,
-                     queue);
-#define KNIT_LAUNCH(RG, NT)                                                                                   \
-  hipLaunchKernelGGL((ldos_mfma_kernel<RG, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite, sigmaL, \
-                     sigmaR, stride, ldos, pstatus, w, slab, Mpmax, Lmax, queue, order, tune.outer)
-  if (precision == KNIT_FP64) {
-    if (tune.threads == 256) KNIT_LAUNCH(double, 256); else KNIT_LAUNCH(double, 512);
-  } else {
-    if (tune.threads == 256) KNIT_LAUNCH(float, 256); else KNIT_LAUNCH(float, 512);
-  }
+  const double rtol = sweep_get_refine_threshold();
+  auto pass = [&](int prec, const int32_t *redo) -> hipError_t {
+    const knit_sweep_tuning tune = sweep_tuning_get(prec, Mpmax);
+    const size_t slab = ldos_mfma_slab_bytes(Mmax, Lmax, stride, prec, table_has_dense(tab));
+    int grid = tune.wg_per_cu * ncu;
+    if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+    if (grid > P) grid = P;
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr,
+                       order, queue);
+#define KNIT_LAUNCH(RG, RS, RF, NT)                                                                            \
+  hipLaunchKernelGGL((ldos_mfma_kernel<RG, RS, RF, NT>), dim3(grid), dim3(NT), 0, stream, tab, probs, P, onsite,   \
+                     sigmaL, sigmaR, stride, ldos, pstatus, w, slab, Mpmax, Lmax, queue, order, tune.outer, rtol,  \
+                     redo)
+    const bool small = tune.threads == 256;
+    if (prec == KNIT_FP64) {
+      if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
+    } else if (prec == KNIT_FP32) {
+      if (small) KNIT_LAUNCH(float, float, false, 256); else KNIT_LAUNCH(float, float, false, 512);
+    } else {
+      if (small) KNIT_LAUNCH(float, double, true, 256); else KNIT_LAUNCH(float, double, true, 512);
+    }
 #undef KNIT_LAUNCH
-  return hipGetLastError();
+    return hipGetLastError();
+  };
+  hipError_t err = pass(precision, nullptr);
+  if (err != hipSuccess || precision != KNIT_FP32_REFINE) return err;
+  return pass(KNIT_FP64, pstatus);
 }
 
 hipError_t launch_sweep_projected(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
-                                  const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, knit_z *G1Np,
-                                  knit_z *GNN, int32_t *pstatus, void *ws, int Mmax, hipStream_t stream) {
+                                  const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, int precision,
+                                  knit_z *G1Np, knit_z *GNN, int32_t *pstatus, void *ws, int Mmax, int max_grid,
+                                  hipStream_t stream) {
   unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
   int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
   int *rows = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256 + order_bytes(P));
@@ -1192,23 +1440,36 @@ hipError_t launch_sweep_projected(const StripTable &tab, const knit_problem *pro
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  const knit_sweep_tuning tune = sweep_tuning_get(KNIT_FP64, Mpmax);
-  const size_t slab = sweep_mfma_slab_bytes(Mmax, KNIT_FP64);
-  int grid = tune.wg_per_cu * ncu;
-  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
-  if (grid > P) grid = P;
+  const double rtol = sweep_get_refine_threshold();
   hipLaunchKernelGGL(proj_rows_kernel, dim3(P), dim3(256), 0, stream, tab, probs, P, CL, rows);
-  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)rows, order,
-                     queue);
-  if (tune.threads == 256)
-    hipLaunchKernelGGL((sweep_mfma_kernel<double, double, false, 256, true>), dim3(grid), dim3(256), 0, stream, tab,
-                       probs, P, onsite, sigmaL, sigmaR, G1Np, (knit_z *)nullptr, GNN, pstatus, w, slab, Mpmax, queue,
-                       order, 0.0, (const int32_t *)nullptr, tune.outer, CL, rows);
-  else
-    hipLaunchKernelGGL((sweep_mfma_kernel<double, double, false, 512, true>), dim3(grid), dim3(512), 0, stream, tab,
-                       probs, P, onsite, sigmaL, sigmaR, G1Np, (knit_z *)nullptr, GNN, pstatus, w, slab, Mpmax, queue,
-                       order, 0.0, (const int32_t *)nullptr, tune.outer, CL, rows);
-  return hipGetLastError();
+  // one pass at `prec`; redo != NULL restricts it to the problems flagged KNIT_P_FALLBACK
+  auto pass = [&](int prec, const int32_t *redo) -> hipError_t {
+    const knit_sweep_tuning tune = sweep_tuning_get(prec, Mpmax);
+    const size_t slab = sweep_mfma_slab_bytes(Mmax, prec, table_has_dense(tab));
+    int grid = tune.wg_per_cu * ncu;
+    if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    if (grid > P) grid = P;
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)rows,
+                       order, queue);
+#define KNIT_LAUNCH(RG, RS, RF, NT)                                                                            \
+  hipLaunchKernelGGL((sweep_mfma_kernel<RG, RS, RF, NT, true>), dim3(grid), dim3(NT), 0, stream, tab, probs, P,     \
+                     onsite, sigmaL, sigmaR, G1Np, (knit_z *)nullptr, GNN, pstatus, w, slab, Mpmax, queue, order,  \
+                     rtol, redo, tune.outer, CL, rows)
+    const bool small = tune.threads == 256;
+    if (prec == KNIT_FP64) {
+      if (small) KNIT_LAUNCH(double, double, false, 256); else KNIT_LAUNCH(double, double, false, 512);
+    } else if (prec == KNIT_FP32) {
+      if (small) KNIT_LAUNCH(float, float, false, 256); else KNIT_LAUNCH(float, float, false, 512);
+    } else {
+      if (small) KNIT_LAUNCH(float, double, true, 256); else KNIT_LAUNCH(float, double, true, 512);
+    }
+#undef KNIT_LAUNCH
+    return hipGetLastError();
+  };
+  hipError_t err = pass(precision, nullptr);
+  if (err != hipSuccess || precision != KNIT_FP32_REFINE) return err;
+  return pass(KNIT_FP64, pstatus);
 }
 
 size_t inverse_fp64_scratch_elems(int M) {
@@ -1235,22 +1496,29 @@ hipError_t launch_inverse_fp64(cpx<double> *X, int64_t xstride, cpx<double> *scr
 // projected rows [P] (each padded to 256 bytes), then one slab per workgroup.
 
 // The refined sweep's second (FP64) pass shares the workspace.
-static size_t slab_for(int Mmax, int precision) {
-  size_t s = sweep_mfma_slab_bytes(Mmax, precision);
+static size_t slab_for(int Mmax, int precision, bool dense) {
+  size_t s = sweep_mfma_slab_bytes(Mmax, precision, dense);
   if (precision == KNIT_FP32_REFINE) {
-    const size_t s64 = sweep_mfma_slab_bytes(Mmax, KNIT_FP64);
+    const size_t s64 = sweep_mfma_slab_bytes(Mmax, KNIT_FP64, dense);
     if (s64 > s) s = s64;
   }
   return s;
 }
 
-size_t sweep_mfma_workspace(int Mmax, int precision, int P) {
+size_t sweep_mfma_workspace(int Mmax, int precision, int P, bool dense) {
   const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
-  return 256 + 2 * order_bytes(P) + slab_for(Mmax, precision) * (size_t)grid;
+  return 256 + 2 * order_bytes(P) + slab_for(Mmax, precision, dense) * (size_t)grid;
+}
+
+int sweep_mfma_grid_within(size_t bytes, int Mmax, int precision, int P, bool dense) {
+  const size_t head = 256 + 2 * order_bytes(P);
+  if (bytes <= head) return 0;
+  const size_t n = (bytes - head) / slab_for(Mmax, precision, dense);
+  return n > (size_t)SWEEP_MAX_GRID ? SWEEP_MAX_GRID : (int)n;
 }
 
 namespace {
-std::atomic<double> refine_threshold{1e-3};
+std::atomic<double> refine_threshold{0.25};
 }
 
 int sweep_set_refine_threshold(double t) {
@@ -1306,7 +1574,7 @@ knit_sweep_tuning sweep_tuning_get(int precision, int Mpmax) {
 
 hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
                              const knit_z *sigmaL, const knit_z *sigmaR, int precision, knit_z *G1N,
-                             knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, int Mmax,
+                             knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, int Mmax, int max_grid,
                              hipStream_t stream) {
   unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
   int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
@@ -1325,9 +1593,10 @@ hipError_t launch_sweep_mfma(const StripTable &tab, const knit_problem *probs, i
     // slice fits one panel row per thread, else 512 threads, one per unit; LPT)
     const knit_sweep_tuning tune = sweep_tuning_get(prec, Mpmax);
     const bool small = tune.threads == 256;
-    const size_t slab = sweep_mfma_slab_bytes(Mmax, prec);
+    const size_t slab = sweep_mfma_slab_bytes(Mmax, prec, table_has_dense(tab));
     int grid = tune.wg_per_cu * ncu;
     if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
     if (grid > P) grid = P;
     hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr, order,
                      queue);

@@ -52,22 +52,34 @@ SEED_SYNTHETIC_SIGMA = 10102628     # synthetic boundary self-energies of the fu
 
 @dataclass
 class Strip:
-    """Clean strip class: slice Hamiltonian H0 and inter-slice coupling V."""
+    """Clean strip class: slice Hamiltonian H0 and inter-slice coupling V.
+
+    V is block-monomial (``vcol`` / ``vblk``) unless ``V`` holds a dense [M, M]
+    inter-slice hopping (then ``vcol`` / ``vblk`` are None).  ``onsite_dense``
+    strips take their per-slice on-site terms as full [L, M, M] matrices
+    instead of site blocks [L, W, norb, norb]."""
 
     name: str
     W: int
     norb: int
     H0: np.ndarray            # [M, M] complex128
-    vcol: np.ndarray          # [W] int32
-    vblk: np.ndarray          # [W, norb, norb] complex128
+    vcol: np.ndarray | None   # [W] int32
+    vblk: np.ndarray | None   # [W, norb, norb] complex128
     meta: dict = field(default_factory=dict)
+    V: np.ndarray | None = None      # [M, M] complex128, dense inter-slice hopping
+    onsite_dense: bool = False
 
     @property
     def M(self) -> int:
         return self.W * self.norb
 
+    def onsite_shape(self, L: int) -> tuple:
+        return (L, self.M, self.M) if self.onsite_dense else (L, self.W, self.norb, self.norb)
+
     def V_dense(self) -> np.ndarray:
         """Assemble V = H_{n,n-1} as a dense [M, M] matrix."""
+        if self.V is not None:
+            return self.V.copy()
         M, no = self.M, self.norb
         V = np.zeros((M, M), dtype=np.complex128)
         for a in range(self.W):
@@ -81,6 +93,9 @@ def _check(strip: Strip) -> Strip:
     M = strip.M
     assert strip.H0.shape == (M, M) and strip.H0.dtype == np.complex128
     assert np.allclose(strip.H0, strip.H0.conj().T), "H0 must be Hermitian"
+    if strip.V is not None:
+        assert strip.V.shape == (M, M) and strip.V.dtype == np.complex128
+        return strip
     assert strip.vcol.shape == (strip.W,) and strip.vcol.dtype == np.int32
     assert strip.vblk.shape == (strip.W, strip.norb, strip.norb)
     used = strip.vcol[strip.vcol >= 0]
@@ -151,6 +166,52 @@ def zigzag_strip(Nz: int, t: float = 1.0) -> Strip:
     return _check(Strip(f"zigzag_Nz{Nz}", M, 1, H0, vcol, vblk, {"t": t}))
 
 
+def square_nnn_strip(W: int, t: float = 1.0, tp: float = 0.25) -> Strip:
+    """Scalar square-lattice strip with next-nearest-neighbour hopping +tp along the
+    diagonals.  Site y of slice n bonds to sites y-1, y, y+1 of slice n-1, so V =
+    t I + tp (shift up + shift down) is tridiagonal: not block-monomial, a dense
+    coupling for the library."""
+    H0 = np.zeros((W, W), dtype=np.complex128)
+    for y in range(W - 1):
+        H0[y + 1, y] = H0[y, y + 1] = t
+    V = t * np.eye(W, dtype=np.complex128)
+    for y in range(W - 1):
+        V[y + 1, y] = V[y, y + 1] = tp
+    return _check(Strip(f"square_nnn_W{W}", W, 1, H0, None, None, {"t": t, "tp": tp}, V=V))
+
+
+def random_unitary(M: int, seed: int) -> np.ndarray:
+    """Seeded Haar-distributed unitary [M, M] (QR of a complex Gaussian matrix, phases fixed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Z = (rng.normal(size=(M, M)) + 1j * rng.normal(size=(M, M))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R)
+    return Q * (d / np.abs(d))[None, :]
+
+
+def rotated_strip(strip: Strip, U: np.ndarray) -> Strip:
+    """The same strip written in another slice basis: H0 -> U H0 U^+, V -> U V U^+, the
+    same unitary U on every slice and in both leads.  V becomes dense and so do the
+    on-site terms (rotate them with rotated_onsite)."""
+    Ud = U.conj().T
+    H0 = U @ strip.H0 @ Ud
+    H0 = 0.5 * (H0 + H0.conj().T)
+    V = U @ strip.V_dense() @ Ud
+    return _check(Strip(strip.name + "_rotated", strip.W, strip.norb, H0, None, None, dict(strip.meta), V=V,
+                        onsite_dense=True))
+
+
+def rotated_onsite(strip: Strip, onsite: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """On-site terms of ``strip`` (site blocks [L, W, norb, norb]) as full matrices in the
+    rotated basis: [L, M, M] = U blockdiag(onsite[n]) U^+."""
+    L = onsite.shape[0]
+    M, no = strip.M, strip.norb
+    out = np.zeros((L, M, M), dtype=np.complex128)
+    for s_ in range(strip.W):
+        out[:, s_ * no:(s_ + 1) * no, s_ * no:(s_ + 1) * no] = onsite[:, s_]
+    return U[None] @ out @ U.conj().T[None]
+
+
 def onsite_disorder(strip: Strip, L: int, w: float, seed: int) -> np.ndarray:
     """On-site blocks [L, W, norb, norb]: eps * identity with eps ~ U[-w/2, w/2].
 
@@ -168,7 +229,7 @@ def onsite_disorder(strip: Strip, L: int, w: float, seed: int) -> np.ndarray:
 
 
 def clean_onsite(strip: Strip, L: int) -> np.ndarray:
-    return np.zeros((L, strip.W, strip.norb, strip.norb), dtype=np.complex128)
+    return np.zeros(strip.onsite_shape(L), dtype=np.complex128)
 
 
 def synthetic_sigma(M: int, n: int, seed: int = SEED_SYNTHETIC_SIGMA, scale: float = 0.5,

@@ -33,7 +33,11 @@ c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_doubl
 
 
 class KnitStrip(ctypes.Structure):
-    _fields_ = [("M", c_i32), ("norb", c_i32), ("H0", c_vp), ("vcol", c_vp), ("vblk", c_vp)]
+    _fields_ = [("M", c_i32), ("norb", c_i32), ("H0", c_vp), ("vcol", c_vp), ("vblk", c_vp), ("V", c_vp),
+                ("onsite_dense", c_i32), ("reserved", c_i32)]
+
+
+assert ctypes.sizeof(KnitStrip) == 48
 
 
 PROBLEM_DTYPE = np.dtype([("strip", "<i4"), ("L", "<i4"), ("E", "<f8"), ("onsite_off", "<i8"),
@@ -67,8 +71,13 @@ _lib.knit_ldos.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i3
 _lib.knit_gamma_factor.restype = c_i32
 _lib.knit_gamma_factor.argtypes = [c_i32, c_vp, c_i32, c_dbl, c_vp, c_vp, c_vp]
 _lib.knit_rgf_sweep_projected.restype = c_i32
-_lib.knit_rgf_sweep_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
-                                          c_vp, c_vp, c_sz, c_vp]
+_lib.knit_rgf_sweep_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp,
+                                          c_vp, c_vp, c_vp, c_sz, c_vp]
+_lib.knit_transmission_eigenvalues_workspace.restype = c_sz
+_lib.knit_transmission_eigenvalues_workspace.argtypes = [_SP, c_i32, c_vp, c_i32]
+_lib.knit_transmission_eigenvalues.restype = c_i32
+_lib.knit_transmission_eigenvalues.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp,
+                                               c_vp, c_vp, c_sz, c_vp]
 _lib.knit_transmission_projected.restype = c_i32
 _lib.knit_transmission_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]
 
@@ -92,7 +101,8 @@ EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
-            "knit_transmission_projected"]
+            "knit_transmission_projected", "knit_transmission_eigenvalues_workspace",
+            "knit_transmission_eigenvalues"]
 
 
 class KnitError(RuntimeError):
@@ -124,8 +134,8 @@ def knit_sweep_tuning_set(precision, cls: int, threads: int | None = None, wg_pe
 
 
 def knit_set_refine_threshold(threshold: float):
-    """Largest residual entry one FP32-refinement step may start from before the problem is
-    recomputed in FP64 (KNIT_P_FALLBACK)."""
+    """Largest ||I - A_n X0||_F (first residual of a slice's FP32 inverse) the refinement may
+    start from before the problem is recomputed in FP64 (KNIT_P_FALLBACK)."""
     _check(_lib.knit_set_refine_threshold(float(threshold)), "knit_set_refine_threshold")
 
 
@@ -174,19 +184,25 @@ class DeviceStrip:
 
     M: int
     norb: int
-    H0: torch.Tensor      # [M, M] complex128
-    vcol: torch.Tensor    # [W] int32
-    vblk: torch.Tensor    # [W, norb, norb] complex128
+    H0: torch.Tensor             # [M, M] complex128
+    vcol: torch.Tensor | None    # [W] int32 (block-monomial V)
+    vblk: torch.Tensor | None    # [W, norb, norb] complex128 (block-monomial V)
+    V: torch.Tensor | None = None   # [M, M] complex128 (dense V)
+    onsite_dense: bool = False
 
     @classmethod
     def from_host(cls, strip, device="cuda"):
-        return cls(strip.M, strip.norb,
-                   torch.from_numpy(np.ascontiguousarray(strip.H0)).to(device),
-                   torch.from_numpy(np.ascontiguousarray(strip.vcol, dtype=np.int32)).to(device),
-                   torch.from_numpy(np.ascontiguousarray(strip.vblk)).to(device))
+        dense = getattr(strip, "V", None) is not None
+        t = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+        return cls(strip.M, strip.norb, t(strip.H0),
+                   None if dense else t(strip.vcol, np.int32),
+                   None if dense else t(strip.vblk),
+                   t(strip.V) if dense else None,
+                   bool(getattr(strip, "onsite_dense", False)))
 
     def c(self) -> KnitStrip:
-        return KnitStrip(self.M, self.norb, _ptr(self.H0), _ptr(self.vcol), _ptr(self.vblk))
+        return KnitStrip(self.M, self.norb, _ptr(self.H0), _ptr(self.vcol), _ptr(self.vblk), _ptr(self.V),
+                         int(self.onsite_dense), 0)
 
 
 def strip_table(strips) -> ctypes.Array:
@@ -342,8 +358,10 @@ def knit_gamma_factor(M: int, sigma: torch.Tensor, n: int, tol: float = 0.0, C: 
 
 
 def knit_rgf_sweep_projected(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, CL, G1Np=None,
-                             GNN: torch.Tensor | bool = False, stream=None, workspace: torch.Tensor | None = None):
-    """Projected sweep (FP64): returns (G1Np, GNN|None, status) with P_L = C_L^+ G_1L at out_off."""
+                             GNN: torch.Tensor | bool = False, stream=None, workspace: torch.Tensor | None = None,
+                             precision="fp64"):
+    """Projected sweep: returns (G1Np, GNN|None, status) with P_L = C_L^+ G_1L at out_off."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     tab = strip_table(strips)
     dev = onsite.device
     P = probs.P
@@ -354,11 +372,11 @@ def knit_rgf_sweep_projected(strips, probs: ProblemTable, onsite, sigmaL, sigmaR
         GNN = torch.empty(need, dtype=torch.complex128, device=dev)
     GNN = GNN if isinstance(GNN, torch.Tensor) else None
     status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
-    wsz = _lib.knit_rgf_sweep_workspace(tab, len(strips), _ptr(probs.host), P, KNIT_FP64, 0)
+    wsz = _lib.knit_rgf_sweep_workspace(tab, len(strips), _ptr(probs.host), P, prec, 0)
     if workspace is None or workspace.numel() < wsz:
         workspace = torch.empty(max(int(wsz), 1), dtype=torch.uint8, device=dev)
     code = _lib.knit_rgf_sweep_projected(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P,
-                                         _ptr(_z(onsite)), _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(_z(CL)),
+                                         _ptr(_z(onsite)), _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(_z(CL)), prec,
                                          _ptr(G1Np), _ptr(GNN), _ptr(status), _ptr(workspace),
                                          workspace.numel(), _stream(stream))
     _check(code, "knit_rgf_sweep_projected")
@@ -373,6 +391,28 @@ def knit_transmission_projected(strips, probs: ProblemTable, CR, G1Np, stream=No
                                             _ptr(_z(CR)), _ptr(_z(G1Np)), _ptr(T), _stream(stream))
     _check(code, "knit_transmission_projected")
     return T[:probs.P]
+
+
+def knit_transmission_eigenvalues(strips, probs: ProblemTable, CR, G1Np, stream=None,
+                                  workspace: torch.Tensor | None = None):
+    """Transmission eigenvalues from the projected propagator.  Returns (tn [P, ld] descending,
+    nch [P] int32, T [P], fano [P]) on the device, ld = the largest M of the batch."""
+    tab = strip_table(strips)
+    dev = G1Np.device
+    P = probs.P
+    ld = max(1, max((_strip_M(s) for s in strips), default=1))
+    tn = torch.empty((max(P, 1), ld), dtype=torch.float64, device=dev)
+    nch = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    T = torch.empty(max(P, 1), dtype=torch.float64, device=dev)
+    fano = torch.empty(max(P, 1), dtype=torch.float64, device=dev)
+    wsz = int(_lib.knit_transmission_eigenvalues_workspace(tab, len(strips), _ptr(probs.host), P))
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_transmission_eigenvalues(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(CR)),
+                                              _ptr(_z(G1Np)), ld, _ptr(tn), _ptr(nch), _ptr(T), _ptr(fano),
+                                              _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(code, "knit_transmission_eigenvalues")
+    return tn[:P], nch[:P], T[:P], fano[:P]
 
 
 def _strip_M(s) -> int:

@@ -51,7 +51,7 @@ class Batch:
         offs, chunks, pos = [], [], 0
         for r in self.realizations:
             st = self.strips[r.strip]
-            assert r.onsite.shape[1:] == (st.W, st.norb, st.norb)
+            assert r.onsite.shape[1:] == st.onsite_shape(1)[1:]
             offs.append(pos)
             chunks.append(np.ascontiguousarray(r.onsite, dtype=np.complex128).reshape(-1))
             pos += chunks[-1].size
@@ -133,12 +133,16 @@ class Batch:
                          ((self.realizations[int(m[0])], m) for m in self.prob_meta)], dtype=np.int64)
         return self.rankL.cpu().numpy()[slot], self.rankR.cpu().numpy()[slot]
 
-    def sweep_projected(self, gnn=False, stream=None, workspace=None):
+    def sweep_projected(self, gnn=False, stream=None, workspace=None, precision="fp64"):
         return K.knit_rgf_sweep_projected(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR,
-                                          self.CL, GNN=gnn, stream=stream, workspace=workspace)
+                                          self.CL, GNN=gnn, stream=stream, workspace=workspace, precision=precision)
 
     def transmission_projected(self, G1Np, stream=None):
         return K.knit_transmission_projected(self.dstrips, self.probs, self.CR, G1Np, stream)
+
+    def transmission_eigenvalues(self, G1Np, stream=None):
+        """(T_n [P, ld] descending, channel count [P], T [P], Fano factor [P]) from the projected sweep."""
+        return K.knit_transmission_eigenvalues(self.dstrips, self.probs, self.CR, G1Np, stream)
 
     def set_sigmas(self, sigL_list, sigR_list):
         """Install externally computed self-energies: one [nE, M, M] array per strip class."""

@@ -53,7 +53,7 @@ def test_library_exports_every_sampler_kernel_entry(K):
 
 
 def test_abi_version_and_status_strings(K):
-    assert K.abi_version() == 2
+    assert K.abi_version() == 3
     assert K.status_string(K.KNIT_E_ARG) == "invalid argument"
     assert "singular" in K.status_string(K.KNIT_P_SINGULAR)
 
@@ -262,16 +262,21 @@ def test_projected_path_argument_checks(K):
     probs = _probs([(0, 8, 0.1, 0, 0, 0, 0), (0, 8, 0.2, 0, 0, 256, 0)])
     need = lib.knit_rgf_sweep_workspace(s, 1, probs.ctypes.data, 2, 0, 0)
     sw = lambda **kw: lib.knit_rgf_sweep_projected(
-        s, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, kw.get("CL", FAKE), kw.get("G1Np", FAKE), None,
-        FAKE, kw.get("ws", FAKE), kw.get("wsb", need), None)
+        s, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, kw.get("CL", FAKE), kw.get("prec", 0),
+        kw.get("G1Np", FAKE), None, FAKE, kw.get("ws", FAKE), kw.get("wsb", need), None)
     assert sw(CL=None) == K.KNIT_E_ARG
+    assert sw(prec=5) == K.KNIT_E_ARG
+    # the refined projected sweep needs the refined workspace (its FP64 second pass shares it)
+    need_r = lib.knit_rgf_sweep_workspace(s, 1, probs.ctypes.data, 2, 1, 0)
+    assert need_r >= need
+    assert sw(prec=1, wsb=need_r - 1) == K.KNIT_E_WORKSPACE
     assert sw(G1Np=None) == K.KNIT_E_ARG
     assert sw(wsb=need - 1) == K.KNIT_E_WORKSPACE
     assert sw(ws=None) == K.KNIT_E_WORKSPACE
     wide = (K.KnitStrip * 1)(_strip(M=544))
-    assert lib.knit_rgf_sweep_projected(wide, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+    assert lib.knit_rgf_sweep_projected(wide, 1, probs.ctypes.data, FAKE, 2, FAKE, FAKE, FAKE, FAKE, 0, FAKE, None,
                                         FAKE, FAKE, 1 << 40, None) == K.KNIT_E_UNSUPPORTED
-    assert lib.knit_rgf_sweep_projected(s, 1, None, None, 0, None, None, None, None, None, None, None, None, 0,
+    assert lib.knit_rgf_sweep_projected(s, 1, None, None, 0, None, None, None, None, 0, None, None, None, None, 0,
                                         None) == K.KNIT_OK
     # projected transmission
     tp = lib.knit_transmission_projected

@@ -144,3 +144,62 @@ def test_autotuner_installs_a_valid_entry(tmp_path):
         assert K.knit_sweep_tuning_get("fp64", r["cls"]) == r["best"]
     finally:
         K.knit_sweep_tuning_set("fp64", r["cls"], None)
+
+
+def _replay_equals(g, outs, eager, reps=3):
+    for rep in range(reps):
+        x = torch.randn(1 << 20, device="cuda").cumsum(0)    # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+        del x
+
+
+@gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine"])
+def test_graph_capture_of_a_projected_step_replays_bitwise(prec):
+    """The benchmarked step - self-energies, broadening factors (pivoted Cholesky), the rows
+    count and queue order kernels, the projected sweep (with the refined call's second, FP64
+    launch) and the projected trace - captured once and replayed three times with eager work
+    in between: every replay equals the eager step bit for bit."""
+    b = _uneven(n_energies=3)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b.compute_sigmas()
+        b.compute_gamma_factors()
+        G, _, st = b.sweep_projected(precision=prec)
+        T_eager = b.transmission_projected(G).clone()
+        st_eager = st.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.compute_sigmas()
+        b.compute_gamma_factors()
+        G_g, _, st_g = b.sweep_projected(precision=prec)
+        T_g = b.transmission_projected(G_g)
+    torch.cuda.synchronize()
+    assert int((st_eager & ~8).abs().sum()) == 0
+    _replay_equals(g, [T_g, st_g], [T_eager, st_eager])
+
+
+@gpu
+def test_graph_capture_of_a_refined_whole_propagator_step_replays_bitwise():
+    b = _uneven(n_energies=3)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        b.compute_sigmas()
+        G1N, _, _, st = b.sweep("fp32_refine", gnn=False)
+        T_eager = b.transmission(G1N)[0].clone()
+        st_eager = st.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.compute_sigmas()
+        G1N_g, _, _, st_g = b.sweep("fp32_refine", gnn=False)
+        T_g = b.transmission(G1N_g)[0]
+    torch.cuda.synchronize()
+    _replay_equals(g, [T_g, st_g], [T_eager, st_eager])

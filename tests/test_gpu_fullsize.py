@@ -118,3 +118,46 @@ def test_full_size_spinful_ldos_matches_oracle_and_is_nonnegative():
         E = np.array([b.energies[0][ei]])
         ref = OR.ldos_rgf(st.H0, V, b.realizations[ri].onsite[:24], E, sL[ei:ei + 1], sR[ei:ei + 1])[0]
         assert np.max(np.abs(ld[p] - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10, (ri, ei)
+
+
+@gpu
+def test_headline_lead_self_energies_and_transport_against_stored_oracle_values():
+    """The spinful W=256 lead (slice dim 512) that supplies every headline point: the GPU's
+    decimated self-energies of both leads at two energies of the 64-point grid against the
+    oracle's exact Bloch-mode values (stored by tests/golden/make_c4_lead_reference.py: six rows
+    and the diagonal of each) at 1e-11; the rank of Gamma = the open channels; then end to end
+    on realization 0 (L = 512) - self-energies, broadening factors, projected sweep, trace,
+    transmission eigenvalues - against the oracle's T and T_n at 1e-10."""
+    import os
+    from paper_1010_2627_amd import workload
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "c4_lead_reference.npz"))
+    st = inputs.rashba_strip(256)
+    E = inputs.midpoint_grid(-3.9, 3.9, 64)[ref["energy_index"]]
+    assert np.array_equal(E, ref["E"])
+    b = workload.Batch([st], [workload.Realization(0, inputs.onsite_disorder(st, 512, 2.0, inputs.SEED_BASE))], [E])
+    b.compute_sigmas()
+    b.compute_gamma_factors()
+    G1Np, _, status = b.sweep_projected()
+    T = b.transmission_projected(G1Np).cpu().numpy()
+    tn, nch, Te, F = [x.cpu().numpy() for x in b.transmission_eigenvalues(G1Np)]
+    G1N, _, _, st_full = b.sweep("fp64", gnn=False)
+    T_full = b.transmission(G1N)[0].cpu().numpy()
+    torch.cuda.synchronize()
+    assert int(b.sigma_status.abs().sum()) == 0 and int(status.abs().sum()) == 0
+    assert int(st_full.abs().sum()) == 0
+    rows = ref["rows"]
+    for i in range(len(E)):
+        sLg, sRg = [s.cpu().numpy() for s in b.sigma_of(i)]
+        for got, rr, rd in ((sLg, ref["sigmaL_rows"][i], ref["sigmaL_diag"][i]),
+                            (sRg, ref["sigmaR_rows"][i], ref["sigmaR_diag"][i])):
+            scale = max(1.0, np.abs(rr).max())
+            assert np.max(np.abs(got[rows] - rr)) < 1e-11 * scale, (i, np.max(np.abs(got[rows] - rr)))
+            assert np.max(np.abs(np.diagonal(got) - rd)) < 1e-11 * scale
+    rl, rr_ = b.problem_ranks()
+    assert np.array_equal(rl, ref["nopen"][0]) and np.array_equal(rr_, ref["nopen"][1])
+    scale = np.maximum(1.0, np.abs(ref["T"]))
+    assert np.max(np.abs(T - ref["T"]) / scale) < 1e-10, (T, ref["T"])
+    assert np.max(np.abs(T_full - ref["T"]) / scale) < 1e-10
+    assert np.array_equal(nch, ref["nopen"].min(axis=0))
+    k = ref["Tn"].shape[1]
+    assert np.max(np.abs(tn[:, :k] - ref["Tn"])) < 1e-10

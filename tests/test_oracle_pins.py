@@ -329,3 +329,48 @@ def test_self_energy_is_absorbing():
             for s in (sL[0], sR[0]):
                 ev = np.linalg.eigvalsh(OL.gamma_of(s))
                 assert ev.min() > -1e-9
+
+
+@pytest.mark.parametrize("W", [4, 7])
+def test_clean_nnn_ribbon_transmission_is_channel_count(W):
+    """Next-nearest-neighbour square strip: H0 = t T and V = t I + t' T share the transverse
+    eigenvectors (T the tridiagonal path matrix), so each transverse mode k is a clean chain
+    with site energy eps_k = 2 t cos(k pi / (W + 1)) and hopping v_k = t + 2 t' cos(k pi / (W + 1)),
+    and T(E) = #{k : |E - eps_k| < 2 |v_k|}.  Checks the oracle's self-energies and recursion
+    with a coupling that is not block-monomial."""
+    t, tp = 1.0, 0.3
+    st = inputs.square_nnn_strip(W, t=t, tp=tp)
+    c = np.cos(np.arange(1, W + 1) * np.pi / (W + 1))
+    eps, v = 2 * t * c, t + 2 * tp * c
+    edges = np.concatenate([eps - 2 * np.abs(v), eps + 2 * np.abs(v)])
+    E = inputs.midpoint_grid(-3.5, 3.5, 15)
+    E = E[np.min(np.abs(E[:, None] - edges[None, :]), axis=1) > 2e-2]   # away from the thresholds
+    assert len(E) >= 10
+    expect = np.array([np.sum(np.abs(e - eps) < 2 * np.abs(v)) for e in E], dtype=float)
+    sL, sR = _sigmas(st, E)
+    T = OR.transmission_full(st.H0, st.V_dense(), inputs.clean_onsite(st, 5), E, sL, sR)[0]
+    assert np.max(np.abs(T - expect)) < 1e-9, (T, expect)
+
+
+def test_nnn_strip_rgf_matches_dense_inverse():
+    """Disordered next-nearest-neighbour strip: slice recursion equals the dense inverse."""
+    st = inputs.square_nnn_strip(4, tp=0.3)
+    L = 7
+    on = inputs.onsite_disorder(st, L, 1.8, 17)
+    E = np.array([-2.2, 0.35, 1.9])
+    sL, sR = _sigmas(st, E)
+    r = OR.rgf_forward(st.H0, st.V_dense(), on, E, sL, sR)
+    Hn = OR.slice_hamiltonians(st.H0, on)
+    for i, e in enumerate(E):
+        H = np.zeros((L * st.M, L * st.M), dtype=np.complex128)
+        M = st.M
+        for n in range(L):
+            H[n * M:(n + 1) * M, n * M:(n + 1) * M] = Hn[n]
+            if n > 0:
+                H[n * M:(n + 1) * M, (n - 1) * M:n * M] = st.V_dense()
+                H[(n - 1) * M:n * M, n * M:(n + 1) * M] = st.V_dense().conj().T
+        S = np.zeros_like(H)
+        S[:M, :M] += sL[i]
+        S[-M:, -M:] += sR[i]
+        G = np.linalg.inv(e * np.eye(L * M) - H - S)
+        assert np.max(np.abs(G[:M, -M:] - r["G1N"][i])) < 1e-12
