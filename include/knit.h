@@ -51,6 +51,8 @@ extern "C" {
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */
 #define KNIT_MAX_SELFENERGY_M 512   /* largest slice for knit_lead_selfenergy */
 #define KNIT_TUNING_CLASSES 16      /* padded slice classes 32, 64, .., 512 */
+#define KNIT_NOALLOC_SCRATCH_BYTES (128u << 20)   /* static scratch of knit_rgf_sweep_noalloc, per GPU */
+#define KNIT_NOALLOC_MAX_PROBLEMS 1048576         /* largest P knit_rgf_sweep_noalloc accepts */
 
 typedef struct knit_z { double re, im; } knit_z;
 
@@ -60,7 +62,9 @@ enum {
   KNIT_E_ARG = -1,          /* invalid argument (nothing was enqueued) */
   KNIT_E_DEVICE = -2,       /* a HIP call failed */
   KNIT_E_WORKSPACE = -3,    /* ws is NULL or ws_bytes is below the *_workspace() size */
-  KNIT_E_UNSUPPORTED = -4   /* valid request this build does not implement */
+  KNIT_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  KNIT_E_SCRATCH = -5       /* knit_rgf_sweep_noalloc: the request does not fit the
+                               library's static scratch (nothing was enqueued) */
 };
 
 /* Per-problem status bits (int32 per problem, written on the device). */
@@ -264,6 +268,27 @@ int knit_rgf_sweep(const knit_strip *strips, int32_t n_strips, const knit_proble
                    const knit_z *sigmaL, const knit_z *sigmaR, int32_t precision, knit_z *G1N,
                    knit_z *GN1, knit_z *GNN, int32_t *pstatus, void *ws, size_t ws_bytes,
                    void *stream);
+
+/*
+ * knit_rgf_sweep without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops, harnesses
+ * that forbid allocation).  Same arguments, outputs and status words as
+ * knit_rgf_sweep (FP64 outputs equal it bit for bit); the call allocates
+ * nothing.  Its work memory is a static device array of
+ * KNIT_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, which each GPU the library
+ * runs on holds until the process ends; the sweep runs as many resident
+ * workgroups as that array holds slice slabs (at slice dimension 512, three),
+ * so large batches run slower than with a full-size workspace.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race and must be serialised by the caller.  Nothing in
+ * the array needs to start at zero (the queue counter is reset on the device
+ * by each call).  Returns KNIT_E_SCRATCH, enqueuing nothing, for P above
+ * KNIT_NOALLOC_MAX_PROBLEMS, and KNIT_E_UNSUPPORTED for strips with M > 512.
+ */
+int knit_rgf_sweep_noalloc(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                           const knit_problem *probs_dev, int32_t P, const knit_z *onsite, const knit_z *sigmaL,
+                           const knit_z *sigmaR, int32_t precision, knit_z *G1N, knit_z *GN1, knit_z *GNN,
+                           int32_t *pstatus, void *stream);
 
 /*
  * Fisher-Lee transmission (section 2.3, T_kl), FP64, per problem:

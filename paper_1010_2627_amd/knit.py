@@ -19,7 +19,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libknit.so")
 
-KNIT_OK, KNIT_E_ARG, KNIT_E_DEVICE, KNIT_E_WORKSPACE, KNIT_E_UNSUPPORTED = 0, -1, -2, -3, -4
+KNIT_OK, KNIT_E_ARG, KNIT_E_DEVICE, KNIT_E_WORKSPACE, KNIT_E_UNSUPPORTED, KNIT_E_SCRATCH = 0, -1, -2, -3, -4, -5
+KNIT_NOALLOC_SCRATCH_BYTES = 128 << 20
+KNIT_NOALLOC_MAX_PROBLEMS = 1048576
 KNIT_P_OK, KNIT_P_SINGULAR, KNIT_P_NOCONV, KNIT_P_NONFINITE, KNIT_P_FALLBACK = 0, 1, 2, 4, 8
 KNIT_FP64, KNIT_FP32_REFINE, KNIT_FP32 = 0, 1, 2
 PRECISIONS = {"fp64": KNIT_FP64, "fp32_refine": KNIT_FP32_REFINE, "fp32": KNIT_FP32}
@@ -59,6 +61,9 @@ _lib.knit_rgf_sweep_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32, c_i32]
 _lib.knit_rgf_sweep.restype = c_i32
 _lib.knit_rgf_sweep.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp,
                                 c_vp, c_vp, c_vp, c_sz, c_vp]
+_lib.knit_rgf_sweep_noalloc.restype = c_i32
+_lib.knit_rgf_sweep_noalloc.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp,
+                                        c_vp, c_vp, c_vp]
 _lib.knit_transmission.restype = c_i32
 _lib.knit_transmission.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp]
@@ -101,7 +106,7 @@ EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
-            "knit_transmission_projected", "knit_transmission_eigenvalues_workspace",
+            "knit_transmission_projected", "knit_rgf_sweep_noalloc", "knit_transmission_eigenvalues_workspace",
             "knit_transmission_eigenvalues"]
 
 
@@ -285,6 +290,28 @@ def knit_rgf_sweep(strips, probs: ProblemTable, onsite: torch.Tensor, sigmaL: to
                                _ptr(GNN), _ptr(status), _ptr(workspace), workspace.numel(),
                                _stream(stream))
     _check(code, "knit_rgf_sweep")
+    return G1N, GN1, GNN, status[:P]
+
+
+def knit_rgf_sweep_noalloc(strips, probs: ProblemTable, onsite: torch.Tensor, sigmaL: torch.Tensor,
+                           sigmaR: torch.Tensor, precision="fp64", G1N: torch.Tensor = None,
+                           GN1: torch.Tensor | None = None, GNN: torch.Tensor | None = None,
+                           status: torch.Tensor | None = None, stream=None):
+    """knit_rgf_sweep with the library's static scratch as work memory: the C call allocates
+    nothing.  Outputs and the status word buffer are the caller's (allocated here only when not
+    given, before the call).  Returns (G1N, GN1, GNN, status)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    if G1N is None:
+        G1N = torch.empty(_out_elems(strips, probs), dtype=torch.complex128, device=dev)
+    if status is None:
+        status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    code = _lib.knit_rgf_sweep_noalloc(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
+                                       _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), prec, _ptr(G1N), _ptr(GN1), _ptr(GNN),
+                                       _ptr(status), _stream(stream))
+    _check(code, "knit_rgf_sweep_noalloc")
     return G1N, GN1, GNN, status[:P]
 
 
