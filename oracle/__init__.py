@@ -21,6 +21,9 @@ Contents
             G_l^< = i G Gamma_l G^dagger (section 2.3), and the local
             observables built on it: injected density and spin (on-site
             blocks), longitudinal and transverse currents into every site.
+``multiterminal``  the conductance matrix T_kl = Tr[Gamma_k G_kl Gamma_l
+            G_kl^dagger] of a strip with further leads attached to single
+            slices (section 2.3, section 6.1), by one dense inverse.
 ``noise``   transmission eigenvalues (eigenvalues of t t^dagger with
             t = Gamma_R^{1/2} G_N1 Gamma_L^{1/2}) and the shot-noise Fano
             factor, section 2.1 item (a).
@@ -38,6 +41,7 @@ from .rgf import (rgf_forward, transmission_lr, transmission_rl, transmission_wa
 from .dense import dense_green, dense_strip_hamiltonian, dense_transmission, dense_ldos
 from .noise import psd_sqrt, transmission_amplitude, transmission_eigenvalues, fano_factor
 from .lesser import strip_green_dense, injected_spectral, local_observables
+from .multiterminal import green_with_leads, conductance_matrix
 
 __all__ = [
     "surface_gf_decimation", "sigma_left", "sigma_right", "sigma_square_modal", "sigma_modes",
@@ -46,4 +50,5 @@ __all__ = [
     "dense_green", "dense_strip_hamiltonian", "dense_transmission", "dense_ldos",
     "psd_sqrt", "transmission_amplitude", "transmission_eigenvalues", "fano_factor",
     "strip_green_dense", "injected_spectral", "local_observables",
+    "green_with_leads", "conductance_matrix",
 ]
