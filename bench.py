@@ -9,11 +9,13 @@ One step = the whole T(E) path over the batch, with the inputs resident in HBM:
     projected propagator C_L^+ G_1n;
   * the Fisher-Lee trace T = ||C_L^+ G_1L C_R||^2.
 
-Beside the headline, full steps of two other paths are timed:
+Beside the headline, full steps of three other paths are timed:
   * the FP64 sweep carrying the whole G_1n (and the full trace);
-  * the FP32 matrix-core sweep with one FP64-residual refinement per slice
-    inverse (whole G_1n).
-Their T(E) is compared with the headline's, per open channel.  The headline
+  * the refined paths, projected and whole G_1n: FP32 matrix-core elimination
+    of each slice with FP64-residual Newton steps on its inverse and the
+    propagator as an FP64 product of the refined inverse.
+Their T(E) is compared with the FP64 one of the same path, per open channel,
+with the count of problems the refinement handed to FP64.  The headline
 `value` is the step throughput of the projected FP64 path, which meets the
 tolerance at every point; the others' figures sit beside it.
 
@@ -159,7 +161,21 @@ def sampler_bench(args, cfg):
     print(json.dumps(out))
 
 
-def cpu_baseline(cfg, b, budget_s=20.0):
+def cpu_baseline(cfg, b, budget_s=20.0, single_thread_s=8.0):
+    """The oracle on a bounded sample, with all host threads, then again with one thread
+    (threadpoolctl) on a smaller sample; both rates in slice-steps/s."""
+    out = _cpu_baseline(cfg, b, budget_s)
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            one = _cpu_baseline(cfg, b, single_thread_s, n_energies=1)
+        out["single_thread"] = {"value": one["value"], "unit": one["unit"], "cores": 1, "sample": one["sample"]}
+    except ImportError:                                                 # pragma: no cover
+        out["single_thread"] = None
+    return out
+
+
+def _cpu_baseline(cfg, b, budget_s=20.0, n_energies=None):
     """The CPU oracle on a bounded sample of the same workload (oracle untuned).
 
     Up to M = 256 the sample includes the oracle's own lead self-energies (Bloch-mode
@@ -171,14 +187,14 @@ def cpu_baseline(cfg, b, budget_s=20.0):
     from oracle import rgf as OR
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] + [1])
     except Exception:                                                  # pragma: no cover
         threads = os.cpu_count() or 1
     r0 = b.realizations[0]
     st = b.strips[r0.strip]
     V = st.V_dense()
     E_all = np.asarray(b.energies[r0.strip])
-    nE = 4 if st.M <= 256 else 2
+    nE = n_energies or (4 if st.M <= 256 else 2)
     idx = np.linspace(0, len(E_all) - 1, nE).astype(int)
     E = E_all[idx]
     on = r0.onsite
@@ -223,11 +239,16 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS (backward sweep) timing")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline (projected FP64) step only: no other paths, no CPU baseline "
+                         "(for profiler runs)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the sweep's launch shapes on a sample of the batch first and use the best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.headline_only:
+        args.no_mixed = args.no_ldos = args.no_cpu_baseline = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "is described, not run)"}))
@@ -334,10 +355,10 @@ def main():
     # algorithmic flops of the projected sweep per slice: the slice inverse (8 M^3) and the
     # product P_{n-1} V^+ g_n with r = rank(Gamma_L) rows (8 M^2 r)
     flops_proj = float(np.sum((8.0 * Ms ** 3 + 8.0 * Ms ** 2 * rankL) * b.probs.host["L"]))
-    T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", 1)
-    progress(f"fp64 full propagator: {wall64:.2f} s/step (sweep {tw64:.2f} s)")
+    if not args.headline_only:
+        T64, wall64, (ts64, tw64, tt64), bad64 = timed("fp64", 1)
+        progress(f"fp64 full propagator: {wall64:.2f} s/step (sweep {tw64:.2f} s)")
     nopen = open_channels(b)
-    dTp = np.abs(Tp - T64) / np.maximum(1, nopen)
     ldos_info = None
     if not args.no_ldos:
         # local density of states (backward sweep with checkpoints): the whole batch with every
@@ -407,14 +428,14 @@ def main():
                      "flops_per_slice_step": "8*M^3 + 8*M^2*r (inverse + projected propagator, r = rank "
                                              "Gamma_L)",
                      "flops_per_step": flops_proj},
-        "fp64_full_propagator": {
+        "fp64_full_propagator": None if args.headline_only else {
             "slice_steps_per_s": steps_per_pass / wall64,
             "sweep_s": round(float(tw64), 4),
             "sweep_slice_steps_per_s": steps_per_pass / tw64,
             "tflops_at_16M3": flops_full / tw64 / 1e12,
             "frac_of_fp64_peak": flops_full / tw64 / 1e12 / PEAK_TFLOPS["fp64"],
             "projected_sweep_speedup": tw64 / twp,
-            "max_dT_per_open_channel_projected_vs_full": float(dTp.max()),
+            "max_dT_per_open_channel_projected_vs_full": float((np.abs(Tp - T64) / np.maximum(1, nopen)).max()),
             "problems_with_status": bad64,
         },
     }

@@ -181,7 +181,9 @@ const char *knit_status_string(int code);
  *   strip     host   strip class
  *   side      0 = left lead, 1 = right lead, 2 = both
  *   E         device [nE] energies
- *   eta       broadening, > 0 (1e-13 recommended)
+ *   eta       broadening, > 0 (1e-16 recommended: the result is biased by about
+ *             eta / velocity, which stays below 1e-12 even 1e-9 from a channel
+ *             threshold, where the slowest open mode has velocity ~ 6e-5)
  *   sigma     device [nE][M][M] output; side 2: [2][nE][M][M], left block first
  *   iters     device [nE] output iteration counts, or NULL
  *   pstatus   device [nE] output status words
@@ -409,6 +411,39 @@ int knit_transmission_eigenvalues(const knit_strip *strips, int32_t n_strips, co
                                   const knit_problem *probs_dev, int32_t P, const knit_z *CR, const knit_z *G1Np,
                                   int32_t ld, double *tn, int32_t *nch, double *T, double *fano, void *ws,
                                   size_t ws_bytes, void *stream);
+
+/*
+ * Lesser Green function of injection from the left lead and the local
+ * observables built on it (section 2.3: G_L^< = i G Gamma_L G^+, electrons
+ * injected with probability 1 from the left lead; sections 5.3-D, 6.1 and 6.2:
+ * local densities, local currents, spin accumulation), FP64.  With
+ * Gamma_L = C_L C_L^+ (knit_gamma_factor), A_L = -i G_L^< = Q Q^+ with the
+ * slice blocks Q_n = G_{n1} C_L of the full Green function; a forward sweep
+ * keeps checkpoints of g_n and g^L_{n1} C_L every `checkpoint_stride` slices
+ * (<= 0: ceil(sqrt(L))), the reverse sweep forms Q_n from Dyson's equation
+ * across each inter-slice cut.  Per problem p, slice n, site s (norb orbitals):
+ *   blk[blk_off[p] + ((n W + s) norb + o) norb + o'] = A_L(n s o, n s o')
+ *       on-site blocks (complex, [L][W][norb][norb]): Tr / (2 pi) is the
+ *       density injected from the left lead per unit energy, A_00 - A_11 the
+ *       sigma_z spin density of section 6.2
+ *   jlong[ldos_off + n W + s] = current into site s of slice n from slice n-1,
+ *       sum over its bonds of 2 Im Tr[H_ab A_ba] (units e/h per unit energy;
+ *       0 for n = 0); over any cross-section it sums to the transmission T
+ *   jtran[ldos_off + n W + s] = current into site s from the other sites of
+ *       its own slice (sums to 0 over each slice)
+ * A right-lead injection is the same call on the mirrored strip (slices in
+ * reverse order, V replaced by V^+).  blk_off is device int64 [P]; jlong and
+ * jtran use the first L W doubles of each problem's [L][M] LDOS slot.  M > 512
+ * returns KNIT_E_UNSUPPORTED.  The workspace is
+ * knit_local_observables_workspace() bytes.
+ */
+size_t knit_local_observables_workspace(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                        int32_t P, int32_t checkpoint_stride);
+int knit_local_observables(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                           const knit_problem *probs_dev, int32_t P, const knit_z *onsite, const knit_z *sigmaL,
+                           const knit_z *sigmaR, const knit_z *CL, int32_t checkpoint_stride, knit_z *blk,
+                           const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus, void *ws,
+                           size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

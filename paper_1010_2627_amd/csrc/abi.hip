@@ -326,4 +326,34 @@ int knit_transmission_eigenvalues(const knit_strip *strips, int32_t n_strips, co
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 
+size_t knit_local_observables_workspace(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                        int32_t P, int32_t checkpoint_stride) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return 0;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
+  if (P == 0 || !sweep_mfma_supports(Mmax)) return 0;
+  return lesser_mfma_workspace(Mmax, Lmax, resolve_stride(checkpoint_stride, Lmax), P, any_dense_v(strips, n_strips));
+}
+
+int knit_local_observables(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                           const knit_problem *probs_dev, int32_t P, const knit_z *onsite, const knit_z *sigmaL,
+                           const knit_z *sigmaR, const knit_z *CL, int32_t checkpoint_stride, knit_z *blk,
+                           const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus, void *ws,
+                           size_t ws_bytes, void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !onsite || !sigmaL || !sigmaR || !CL || !blk || !blk_off || !jlong || !jtran || !pstatus)
+    return KNIT_E_ARG;
+  if (!sweep_mfma_supports(Mmax)) return KNIT_E_UNSUPPORTED;
+  const int st = resolve_stride(checkpoint_stride, Lmax);
+  const size_t need = knit_local_observables_workspace(strips, n_strips, probs_host, P, checkpoint_stride);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_lesser_mfma(tab, probs_dev, P, onsite, sigmaL, sigmaR, CL, st, blk, blk_off, jlong, jtran,
+                                      pstatus, ws, Mmax, Lmax, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
 }  // extern "C"

@@ -19,8 +19,10 @@
 // delta in them grows like 2^k delta while eta must be tiny (the bias of the
 // result is of order eta / velocity), and k ~ log2(1/eta).  In FP64 the error
 // floor is about sqrt(eps_64) ~ 1e-8, far above the 1e-10 the transmission
-// must meet; with ~106-bit arithmetic the same iteration reaches eta = 1e-13
-// with rounding far below it.
+// must meet; with ~106-bit arithmetic the same iteration reaches eta = 1e-16
+// (about 60 steps, rounding growth 2^60 * 1e-32 ~ 1e-14) and keeps the bias
+// eta / velocity below 1e-12 even 1e-9 from a channel threshold, where the
+// newly open mode is slow.
 //
 // Both leads from one run: swapping alpha and beta leaves the doubling
 // unchanged (g_k, eps and the pair {a, b} are symmetric in the swap), so the

@@ -99,6 +99,12 @@ hipError_t launch_gamma_factor(int M, const knit_z *sigma, int n, double tol, kn
 hipError_t launch_transmission_proj(const StripTable &tab, const knit_problem *probs, int P, const knit_z *CR,
                                     const knit_z *G1Np, double *T, hipStream_t stream);
 
+size_t lesser_mfma_workspace(int Mmax, int Lmax, int stride, int P, bool dense);
+hipError_t launch_lesser_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                              const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, int stride,
+                              knit_z *blk, const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus,
+                              void *ws, int Mmax, int Lmax, hipStream_t stream);
+
 size_t transmission_eigs_workspace(int Mmax, int P);
 hipError_t launch_transmission_eigs(const StripTable &tab, const knit_problem *probs, int P, int Mmax,
                                     const knit_z *CR, const knit_z *G1Np, int ld, double *tn, int32_t *nch,

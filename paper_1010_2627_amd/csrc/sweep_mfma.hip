@@ -1329,6 +1329,269 @@ ldos_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z 
   }
 }
 
+// Y = V^+ Gm on the first `ncols` columns for a block-monomial V: row block
+// vcol[a] of Y is vblk[a]^+ times row block a of Gm (each site of slice n-1
+// receives from at most one site of slice n); other rows are zero.
+template <class RS>
+__device__ void scatter_vdag(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, int Mp, int ncols) {
+  const int M = s.M, no = s.norb, W = M / no;
+  for (int64_t i = threadIdx.x; i < (int64_t)Mp * Mp; i += blockDim.x) Y[i] = cpx<RS>{0, 0};
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < (int64_t)W * ncols; i += blockDim.x) {
+    const int a = (int)(i / ncols), c = (int)(i % ncols), cb = s.vcol[a];
+    if (cb < 0) continue;
+    for (int ob = 0; ob < no; ++ob) {
+      cpx<double> acc = {0.0, 0.0};
+      for (int oa = 0; oa < no; ++oa)
+        acc = c_fma(c_conj(vblk_at(s, a, oa, ob)), cvt<double>(Gm[(int64_t)(a * no + oa) * Mp + c]), acc);
+      Y[(int64_t)(cb * no + ob) * Mp + c] = cvt<RS>(acc);
+    }
+  }
+}
+
+// Lesser Green function of injection from the left lead and its local
+// observables (section 2.3: G_L^< = i G Gamma_L G^+; sections 5.3-D and 6:
+// local densities, currents and spin accumulation), FP64, on the matrix
+// cores, one workgroup per problem from the same queue as the sweep.  With
+// Gamma_L = C_L C_L^+ (r columns), A_L = -i G_L^< = Q Q^+ where the slice
+// blocks Q_n = G_{n1} C_L of the full Green function follow from
+//   forward:  g_n = A_n^{-1},  N_1 = g_1 C_L,  N_n = g_n (V N_{n-1})
+//             (N_n = g^L_{n1} C_L, left-connected; g_n and N_n kept every
+//             `stride` slices as checkpoints),
+//   reverse:  Q_L = N_L,  Q_n = N_n + g_n (V^+ Q_{n+1})   (Dyson's equation
+//             across the cut between slices n and n+1), segment by segment
+//             from the checkpoints.
+// Per slice n and site s (orbitals o of s, k < r):
+//   blk[n][s][o][o']  = sum_k Q_n[o,k] conj(Q_n[o',k])          (on-site block of A_L)
+//   jtran[n][s]       = 2 Im sum_o sum_k (H0 Q_n)[o,k] conj(Q_n[o,k])  (inflow from slice n's other sites)
+//   jlong[n+1][s]     = 2 Im sum_o sum_k (V Q_n)[o,k] conj(Q_{n+1}[o,k]) (inflow from slice n)
+// (the on-site terms D_n and the diagonal blocks of H0 drop out of the
+// imaginary parts: Tr of a product of two Hermitian matrices is real);
+// jlong[0] = 0.  With full on-site matrices (onsite_dense) their inter-site
+// terms join H0 in the transverse currents.  Slab (Mp^2 elements each): X,
+// the slice Hamiltonian H_n padded, U, Qa, Qb, the segment's g and N
+// [max(st, 2)] each, their checkpoints [ceil(Lmax / st)] each, V and V^+
+// (used with a dense V, reserved in every slab), then the elimination scratch.
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z *onsite, const knit_z *sigmaL,
+                   const knit_z *sigmaR, const knit_z *CL, const int *rows, int stride, knit_z *blk,
+                   const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus, char *ws,
+                   size_t slab_bytes, int Mpmax, int Lmax, unsigned int *queue, const int *order, int outer) {
+  using C = cpx<double>;
+  __shared__ int next_p;
+  __shared__ int q[NT], pinv[NT];
+  __shared__ double sv[32];
+  __shared__ int si[64];
+  __shared__ C xchg[2 * 32];
+  __shared__ C prow[32];
+  __shared__ double rowv[512];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nw = nt >> 6, wave = tid >> 6, lane = tid & 63;
+  const int64_t EE = (int64_t)Mpmax * Mpmax;
+  const int segbuf = stride < 2 ? 2 : stride;
+  const int nsegmax = (Lmax + stride - 1) / stride;
+  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  C *X = reinterpret_cast<C *>(slab);
+  C *H0p = X + EE, *U = H0p + EE, *Qa = U + EE, *Qb = Qa + EE;
+  C *segg = Qb + EE;                               // [segbuf][Mp][Mp]
+  C *segN = segg + (int64_t)segbuf * EE;           // [segbuf][Mp][Mp]
+  C *cpg = segN + (int64_t)segbuf * EE;            // [nsegmax][Mp][Mp]
+  C *cpN = cpg + (int64_t)nsegmax * EE;            // [nsegmax][Mp][Mp]
+  C *Vd = cpN + (int64_t)nsegmax * EE, *Vh = Vd + EE;   // dense V only
+  C *Sb = Vh + EE;                                 // [2 Mp][NO] scratch
+  C *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;        // [NO][Mp]   scratch
+  const double qnan = __builtin_nan("");
+  for (;;) {
+    if (tid == 0) next_p = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int pi = next_p;
+    __syncthreads();
+    if (pi >= P) break;
+    const int p = order[pi];
+    const knit_problem pr = probs[p];
+    const StripDev s = tab.s[pr.strip];
+    const int M = s.M, no = s.norb, W = M / no, L = pr.L;
+    const int Mp = (M + MPAD - 1) / MPAD * MPAD;
+    const int64_t E2 = (int64_t)Mp * Mp;
+    const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
+    const int r = rows[p], rp = (r + MPAD - 1) / MPAD * MPAD;
+    const int nseg = (L + stride - 1) / stride;
+    const bool dense = s.V != nullptr;
+    int flags = 0;
+    for (int64_t i = tid; i < E2; i += nt) {
+      const int a = (int)(i / Mp), b = (int)(i % Mp);
+      H0p[i] = (a < M && b < M) ? ld_z(s.H0 + (int64_t)a * M + b) : C{0.0, 0.0};
+    }
+    if (dense) load_dense_v<double>(Vd, Vh, s, Mp);
+    __syncthreads();
+    // g_n and N_n (natural order) from g_{n-1} and N_{n-1}
+    auto step = [&](int n, const C *gprev, const C *Nprev, C *gdst, C *Ndst) {
+      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * s.onsite_stride();
+      form_blocks<double, false, false>(X, nullptr, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+                                        [=](int rr, int c) { return gprev[(int64_t)rr * Mp + c]; },
+                                        [=](int rr, int c) { return C{0.0, 0.0}; }, -1, !dense);
+      __syncthreads();
+      if (dense && n > 0) dense_coupling<double, double, false>(X, nullptr, Vd, Vh, gprev, nullptr, U, Mp, 0);
+      flags |= outer == 128 ? gj_two_level<double, NT, 128>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
+                            : gj_two_level<double, NT, 64>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
+      for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
+      __syncthreads();
+      for (int64_t i = tid; i < E2; i += nt) {
+        const int a = (int)(i / Mp), b = (int)(i % Mp);
+        gdst[i] = X[(int64_t)q[a] * Mp + pinv[b]];
+      }
+      // U = C_L (slice 1) or V N_{n-1}, on rp columns
+      if (n == 0) {
+        for (int64_t i = tid; i < E2; i += nt) {
+          const int a = (int)(i / Mp), c = (int)(i % Mp);
+          U[i] = (a < M && c < r) ? ld_z(CL + pr.sigma_off + (int64_t)a * M + c) : C{0.0, 0.0};
+        }
+      } else if (dense) {
+        wg_gemm_mfma<double>(Mp, rp, Mp, Vd, Mp, Nprev, Mp, [&](int rr, int c, double &re, double &im) {
+          U[(int64_t)rr * Mp + c] = C{re, im};
+        });
+      } else {
+        gather_vg<double>(U, Nprev, s, Mp);
+      }
+      __syncthreads();
+      wg_gemm_mfma<double>(Mp, rp, Mp, gdst, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
+        Ndst[(int64_t)rr * Mp + c] = C{re, im};
+      });
+      __syncthreads();
+    };
+    // per-row 2 Im sum_k Y[o,k] conj(Z[o,k]) summed over each site's orbitals into out[W]
+    auto site_current = [&](const C *Y, const C *Z, double *out) {
+      for (int o = wave; o < M; o += nw) {
+        double acc = 0.0;
+        for (int k = lane; k < r; k += 64) {
+          const C y = Y[(int64_t)o * Mp + k], z = Z[(int64_t)o * Mp + k];
+          acc += y.im * z.re - y.re * z.im;          // Im(y conj(z))
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) rowv[o] = 2.0 * acc;
+      }
+      __syncthreads();
+      for (int a = tid; a < W; a += nt) {
+        double v = 0.0;
+        for (int o = 0; o < no; ++o) v += rowv[a * no + o];
+        out[a] = v;
+      }
+      __syncthreads();
+    };
+    // forward pass: checkpoint k holds g and N of slice k st - 1 (k >= 1)
+    {
+      C *cg = segg, *pg = segg + E2, *cN = segN, *pN = segN + E2;
+      for (int n = 0; n < L; ++n) {
+        step(n, pg, pN, cg, cN);
+        if ((n + 1) % stride == 0 && n + 1 < L) {
+          const int64_t k = (n + 1) / stride;
+          for (int64_t i = tid; i < E2; i += nt) {
+            cpg[k * E2 + i] = cg[i];
+            cpN[k * E2 + i] = cN[i];
+          }
+          __syncthreads();
+        }
+        C *t = cg; cg = pg; pg = t;
+        t = cN; cN = pN; pN = t;
+      }
+    }
+    // reverse pass, one segment at a time; Qn is Q_n, Qnext Q_{n+1}
+    C *Qn = Qa, *Qnext = Qb;
+    double *jl = jlong + pr.ldos_off, *jt = jtran + pr.ldos_off;
+    knit_z *bo = blk + blk_off[p];
+    for (int k = nseg - 1; k >= 0; --k) {
+      const int n0 = k * stride, n1 = min(L, n0 + stride);
+      for (int n = n0; n < n1; ++n) {
+        const int64_t prevoff = (int64_t)(n - n0 - 1) * E2;
+        const C *gprev = n == n0 ? (k > 0 ? cpg + (int64_t)k * E2 : segg) : segg + prevoff;
+        const C *Nprev = n == n0 ? (k > 0 ? cpN + (int64_t)k * E2 : segN) : segN + prevoff;
+        step(n, gprev, Nprev, segg + (int64_t)(n - n0) * E2, segN + (int64_t)(n - n0) * E2);
+      }
+      for (int n = n1 - 1; n >= n0; --n) {
+        const C *g = segg + (int64_t)(n - n0) * E2, *N = segN + (int64_t)(n - n0) * E2;
+        if (n == L - 1) {
+          for (int64_t i = tid; i < E2; i += nt) Qn[i] = N[i];
+        } else {
+          // Q_n = N_n + g_n (V^+ Q_{n+1})
+          if (dense)
+            wg_gemm_mfma<double>(Mp, rp, Mp, Vh, Mp, Qnext, Mp, [&](int rr, int c, double &re, double &im) {
+              U[(int64_t)rr * Mp + c] = C{re, im};
+            });
+          else
+            scatter_vdag<double>(U, Qnext, s, Mp, rp);
+          __syncthreads();
+          wg_gemm_mfma<double>(Mp, rp, Mp, g, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
+            const int64_t o = (int64_t)rr * Mp + c;
+            Qn[o] = C{N[o].re + re, N[o].im + im};
+          });
+        }
+        __syncthreads();
+        // on-site blocks of A_L = Q Q^+
+        for (int e = wave; e < M * no; e += nw) {
+          const int o = e / no, o2 = (o / no) * no + e % no;    // orbital o, partner o2 of the same site
+          C acc = {0.0, 0.0};
+          for (int kk = lane; kk < r; kk += 64)
+            acc = c_fma(Qn[(int64_t)o * Mp + kk], c_conj(Qn[(int64_t)o2 * Mp + kk]), acc);
+          for (int off = 32; off > 0; off >>= 1) {
+            acc.re += __shfl_xor(acc.re, off, 64);
+            acc.im += __shfl_xor(acc.im, off, 64);
+          }
+          if (lane == 0) st_z(bo + (int64_t)n * M * no + e, acc);
+        }
+        // inflow into slice n+1 from slice n: 2 Im (V Q_n) . conj(Q_{n+1})
+        if (n < L - 1) {
+          if (dense)
+            wg_gemm_mfma<double>(Mp, rp, Mp, Vd, Mp, Qn, Mp, [&](int rr, int c, double &re, double &im) {
+              U[(int64_t)rr * Mp + c] = C{re, im};
+            });
+          else
+            gather_vg<double>(U, Qn, s, Mp);
+          __syncthreads();
+          site_current(U, Qnext, jl + (int64_t)(n + 1) * W);
+        } else {
+          __syncthreads();
+        }
+        // inflow from the other sites of slice n: 2 Im (H_n Q_n) . conj(Q_n); the site
+        // blocks of H_n drop out, so H0 serves unless the on-site terms are full matrices
+        if (s.onsite_dense) {
+          const knit_z *D = onsite + pr.onsite_off + (int64_t)n * s.onsite_stride();
+          for (int64_t i = tid; i < E2; i += nt) {
+            const int a = (int)(i / Mp), b = (int)(i % Mp);
+            C h = {0.0, 0.0};
+            if (a < M && b < M) {
+              const C h0 = ld_z(s.H0 + (int64_t)a * M + b), d = ld_z(D + (int64_t)a * M + b);
+              h = C{h0.re + d.re, h0.im + d.im};
+            }
+            H0p[i] = h;
+          }
+          __syncthreads();
+        }
+        wg_gemm_mfma<double>(Mp, rp, Mp, H0p, Mp, Qn, Mp, [&](int rr, int c, double &re, double &im) {
+          U[(int64_t)rr * Mp + c] = C{re, im};
+        });
+        __syncthreads();
+        site_current(U, Qn, jt + (int64_t)n * W);
+        C *t = Qn; Qn = Qnext; Qnext = t;
+      }
+    }
+    for (int a = tid; a < W; a += nt) jl[a] = 0.0;
+    // non-finite check over the outputs
+    double bad = 0.0;
+    for (int64_t i = tid; i < (int64_t)L * W; i += nt) bad = fmax(bad, fabs(jl[i]) + fabs(jt[i]));
+    for (int64_t i = tid; i < (int64_t)L * M * no; i += nt) bad = fmax(bad, fabs(bo[i].re) + fabs(bo[i].im));
+    if (bad != bad) bad = INFINITY;
+    bad = wg_max_nan(bad, sv);
+    if (!(bad <= 1.79e308)) flags |= KNIT_P_NONFINITE;
+    if (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE)) {
+      for (int64_t i = tid; i < (int64_t)L * W; i += nt) jl[i] = jt[i] = qnan;
+      for (int64_t i = tid; i < (int64_t)L * M * no; i += nt) st_z(bo + i, C{qnan, qnan});
+    }
+    if (tid == 0) pstatus[p] = flags;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
@@ -1424,6 +1687,54 @@ hipError_t launch_ldos_mfma(const StripTable &tab, const knit_problem *probs, in
   hipError_t err = pass(precision, nullptr);
   if (err != hipSuccess || precision != KNIT_FP32_REFINE) return err;
   return pass(KNIT_FP64, pstatus);
+}
+
+size_t lesser_mfma_slab_bytes(int Mmax, int Lmax, int stride, bool dense) {
+  const size_t Mp = (size_t)mfma_padded(Mmax);
+  const size_t EE = Mp * Mp;
+  const size_t segbuf = stride < 2 ? 2 : stride;
+  const size_t nseg = (Lmax + stride - 1) / stride;
+  (void)dense;   // V and V^+ sit before the elimination scratch in every slab
+  size_t b = (7 + 2 * segbuf + 2 * nseg) * EE * 16 + (2 * Mp * NO_MAX + NO_MAX * Mp) * 16;
+  return (b + 255) & ~size_t(255);
+}
+
+size_t lesser_mfma_workspace(int Mmax, int Lmax, int stride, int P, bool dense) {
+  const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
+  return 256 + 2 * order_bytes(P) + lesser_mfma_slab_bytes(Mmax, Lmax, stride, dense) * (size_t)grid;
+}
+
+hipError_t launch_lesser_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                              const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, int stride,
+                              knit_z *blk, const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus,
+                              void *ws, int Mmax, int Lmax, hipStream_t stream) {
+  unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
+  int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
+  int *rows = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256 + order_bytes(P));
+  char *w = reinterpret_cast<char *>(ws) + 256 + 2 * order_bytes(P);
+  const int Mpmax = mfma_padded(Mmax);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  const knit_sweep_tuning tune = sweep_tuning_get(KNIT_FP64, Mpmax);
+  const size_t slab = lesser_mfma_slab_bytes(Mmax, Lmax, stride, table_has_dense(tab));
+  int grid = tune.wg_per_cu * ncu;
+  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+  if (grid > P) grid = P;
+  hipLaunchKernelGGL(proj_rows_kernel, dim3(P), dim3(256), 0, stream, tab, probs, P, CL, rows);
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)rows,
+                     order, queue);
+  if (tune.threads == 256)
+    hipLaunchKernelGGL(lesser_mfma_kernel<256>, dim3(grid), dim3(256), 0, stream, tab, probs, P, onsite, sigmaL,
+                       sigmaR, CL, (const int *)rows, stride, blk, blk_off, jlong, jtran, pstatus, w, slab, Mpmax,
+                       Lmax, queue, order, tune.outer);
+  else
+    hipLaunchKernelGGL(lesser_mfma_kernel<512>, dim3(grid), dim3(512), 0, stream, tab, probs, P, onsite, sigmaL,
+                       sigmaR, CL, (const int *)rows, stride, blk, blk_off, jlong, jtran, pstatus, w, slab, Mpmax,
+                       Lmax, queue, order, tune.outer);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep_projected(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,

@@ -83,6 +83,11 @@ _lib.knit_transmission_eigenvalues_workspace.argtypes = [_SP, c_i32, c_vp, c_i32
 _lib.knit_transmission_eigenvalues.restype = c_i32
 _lib.knit_transmission_eigenvalues.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp,
                                                c_vp, c_vp, c_sz, c_vp]
+_lib.knit_local_observables_workspace.restype = c_sz
+_lib.knit_local_observables_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32]
+_lib.knit_local_observables.restype = c_i32
+_lib.knit_local_observables.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp,
+                                        c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
 _lib.knit_transmission_projected.restype = c_i32
 _lib.knit_transmission_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]
 
@@ -107,7 +112,7 @@ EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
             "knit_transmission_projected", "knit_rgf_sweep_noalloc", "knit_transmission_eigenvalues_workspace",
-            "knit_transmission_eigenvalues"]
+            "knit_transmission_eigenvalues", "knit_local_observables_workspace", "knit_local_observables"]
 
 
 class KnitError(RuntimeError):
@@ -235,7 +240,7 @@ class ProblemTable:
 
 # ---------------------------------------------------------------- entry points
 
-def knit_lead_selfenergy(strip: DeviceStrip, side: int, E: torch.Tensor, eta: float = 1e-13,
+def knit_lead_selfenergy(strip: DeviceStrip, side: int, E: torch.Tensor, eta: float = 1e-16,
                          tol: float = 1e-16, max_iter: int = 100, stream=None):
     """Sigma of the left (side 0) or right (side 1) lead, or of both (side 2), at energies E
     (device float64 [nE]).
@@ -440,6 +445,37 @@ def knit_transmission_eigenvalues(strips, probs: ProblemTable, CR, G1Np, stream=
                                               _ptr(workspace), workspace.numel(), _stream(stream))
     _check(code, "knit_transmission_eigenvalues")
     return tn[:P], nch[:P], T[:P], fano[:P]
+
+
+def knit_local_observables(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, CL, checkpoint_stride: int = 0,
+                           stream=None, workspace: torch.Tensor | None = None):
+    """Injection from the left lead: returns (blk flat complex128 addressed by the returned
+    blk_off [P] (host int64), jlong and jtran flat float64 addressed by ldos_off, status [P])."""
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    n_ld, offs, pos = 1, [], 0
+    for p in probs.host:
+        st = strips[int(p["strip"])]
+        M = _strip_M(st)
+        n_ld = max(n_ld, int(p["ldos_off"]) + int(p["L"]) * M)
+        offs.append(pos)
+        pos += int(p["L"]) * M * int(st.norb)
+    blk_off = np.array(offs, dtype=np.int64)
+    blk = torch.empty(max(pos, 1), dtype=torch.complex128, device=dev)
+    blk_off_d = torch.from_numpy(blk_off).to(dev)
+    jlong = torch.empty(n_ld, dtype=torch.float64, device=dev)
+    jtran = torch.empty(n_ld, dtype=torch.float64, device=dev)
+    status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    wsz = int(_lib.knit_local_observables_workspace(tab, len(strips), _ptr(probs.host), P, int(checkpoint_stride)))
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_local_observables(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
+                                       _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(_z(CL)), int(checkpoint_stride),
+                                       _ptr(blk), _ptr(blk_off_d), _ptr(jlong), _ptr(jtran), _ptr(status),
+                                       _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(code, "knit_local_observables")
+    return blk, blk_off, jlong, jtran, status[:P]
 
 
 def _strip_M(s) -> int:

@@ -91,7 +91,7 @@ class Batch:
     def slice_steps(self) -> int:
         return int(self.probs.host["L"].sum())
 
-    def compute_sigmas(self, eta=1e-13, tol=1e-16, max_iter=100, stream=None):
+    def compute_sigmas(self, eta=1e-16, tol=1e-16, max_iter=100, stream=None):
         self.sigmaL = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
         self.sigmaR = torch.empty(self.sigma_elems, dtype=torch.complex128, device=self.device)
         stats, its = [], []
@@ -139,6 +139,27 @@ class Batch:
 
     def transmission_projected(self, G1Np, stream=None):
         return K.knit_transmission_projected(self.dstrips, self.probs, self.CR, G1Np, stream)
+
+    def local_observables(self, checkpoint_stride=0, stream=None):
+        """Injection from the left lead (needs compute_gamma_factors): per problem the on-site
+        blocks of A_L = G Gamma_L G^+ [L, W, norb, norb] and the currents into every site from
+        the previous slice and from its own slice [L, W].  Returns (blk, blk_off, jlong, jtran,
+        status); see local_block / current_block."""
+        return K.knit_local_observables(self.dstrips, self.probs, self.onsite, self.sigmaL, self.sigmaR, self.CL,
+                                        checkpoint_stride, stream)
+
+    def local_block(self, blk, blk_off, p: int) -> torch.Tensor:
+        row = self.probs.host[p]
+        st = self.strips[int(row["strip"])]
+        L = int(row["L"])
+        o = int(blk_off[p])
+        return blk[o:o + L * st.M * st.norb].view(L, st.W, st.norb, st.norb)
+
+    def current_block(self, flat: torch.Tensor, p: int) -> torch.Tensor:
+        row = self.probs.host[p]
+        st = self.strips[int(row["strip"])]
+        o = int(row["ldos_off"])
+        return flat[o:o + int(row["L"]) * st.W].view(int(row["L"]), st.W)
 
     def transmission_eigenvalues(self, G1Np, stream=None):
         """(T_n [P, ld] descending, channel count [P], T [P], Fano factor [P]) from the projected sweep."""
