@@ -445,6 +445,50 @@ int knit_local_observables(const knit_strip *strips, int32_t n_strips, const kni
                            const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus, void *ws,
                            size_t ws_bytes, void *stream);
 
+/*
+ * A lead attached to one slice of a strip besides the left and right leads
+ * (section 6.1: systems with more than two leads).
+ *   slice      0-based slice it is attached to (0 <= slice < L of its problem)
+ *   sigma_off  offset, in knit_z, of its self-energy [M][M] (acting on that
+ *              slice's orbitals) in `sigmaX` and of its broadening factor
+ *              (Gamma = C C^+, as written by knit_gamma_factor) in `CX`
+ */
+typedef struct knit_lead {
+  int32_t slice;
+  int32_t reserved;
+  int64_t sigma_off;
+} knit_lead;
+
+#define KNIT_MAX_SIDE_LEADS 6
+
+/*
+ * Conductance matrix of strips with several leads (section 2.3:
+ * T_kl = Tr[Gamma_k G_kl Gamma_l G_kl^+], the transmission from lead l to lead
+ * k; section 6.1: the conductance matrix g_kl = (e^2/h) T_kl), FP64.  Lead 0
+ * is the left lead (slice 0: sigmaL, CL at sigma_off), lead 1 the right lead
+ * (slice L-1: sigmaR, CR), leads 2 .. n_side+1 the problem's side leads
+ * side_host[p * n_side + j] (their self-energies join the slice matrix of
+ * their slice).  A forward sweep keeps checkpoints of the left-connected g_n;
+ * the reverse sweep forms the right-connected ones, the full diagonal block at
+ * every slice hosting a lead, and carries each lead's columns G_{n,s} C and
+ * rows C^+ G_{s,n} down the strip by Dyson's equation across every cut; with
+ * K = n_side + 2:
+ *   T[p * K * K + k * K + l] = || C_k^+ G_{s_k s_l} C_l ||_F^2   (all k, l; the
+ *   diagonal is the formula's value, so row and column sums agree).
+ * n_side <= KNIT_MAX_SIDE_LEADS; side_host is host [P][n_side] (validated
+ * before any device call), side_dev its device copy; sigmaX, CX device.
+ * M > 512 returns KNIT_E_UNSUPPORTED.  checkpoint_stride <= 0 picks
+ * ceil(sqrt(L)).  The workspace is knit_conductance_matrix_workspace() bytes.
+ */
+size_t knit_conductance_matrix_workspace(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                         int32_t P, int32_t n_side, int32_t checkpoint_stride);
+int knit_conductance_matrix(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                            const knit_problem *probs_dev, int32_t P, const knit_z *onsite, const knit_z *sigmaL,
+                            const knit_z *sigmaR, const knit_z *CL, const knit_z *CR, int32_t n_side,
+                            const knit_lead *side_host, const knit_lead *side_dev, const knit_z *sigmaX,
+                            const knit_z *CX, int32_t checkpoint_stride, double *T, int32_t *pstatus, void *ws,
+                            size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -356,4 +356,43 @@ int knit_local_observables(const knit_strip *strips, int32_t n_strips, const kni
   return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
 }
 
+size_t knit_conductance_matrix_workspace(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                                         int32_t P, int32_t n_side, int32_t checkpoint_stride) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return 0;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return 0;
+  if (P == 0 || n_side < 0 || n_side > KNIT_MAX_SIDE_LEADS || !sweep_mfma_supports(Mmax)) return 0;
+  return multiterminal_mfma_workspace(Mmax, Lmax, resolve_stride(checkpoint_stride, Lmax), n_side, P);
+}
+
+int knit_conductance_matrix(const knit_strip *strips, int32_t n_strips, const knit_problem *probs_host,
+                            const knit_problem *probs_dev, int32_t P, const knit_z *onsite, const knit_z *sigmaL,
+                            const knit_z *sigmaR, const knit_z *CL, const knit_z *CR, int32_t n_side,
+                            const knit_lead *side_host, const knit_lead *side_dev, const knit_z *sigmaX,
+                            const knit_z *CX, int32_t checkpoint_stride, double *T, int32_t *pstatus, void *ws,
+                            size_t ws_bytes, void *stream) {
+  int Mmax = 0, Lmax = 0;
+  if (!table_ok(strips, n_strips)) return KNIT_E_ARG;
+  if (!problems_ok(strips, n_strips, probs_host, P, &Mmax, &Lmax)) return KNIT_E_ARG;
+  if (n_side < 0 || n_side > KNIT_MAX_SIDE_LEADS) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs_dev || !onsite || !sigmaL || !sigmaR || !CL || !CR || !T || !pstatus) return KNIT_E_ARG;
+  if (n_side > 0) {
+    if (!side_host || !side_dev || !sigmaX || !CX) return KNIT_E_ARG;
+    for (int p = 0; p < P; ++p)
+      for (int j = 0; j < n_side; ++j) {
+        const knit_lead &l = side_host[(int64_t)p * n_side + j];
+        if (l.slice < 0 || l.slice >= probs_host[p].L || l.sigma_off < 0) return KNIT_E_ARG;
+      }
+  }
+  if (!sweep_mfma_supports(Mmax)) return KNIT_E_UNSUPPORTED;
+  const int st = resolve_stride(checkpoint_stride, Lmax);
+  const size_t need = knit_conductance_matrix_workspace(strips, n_strips, probs_host, P, n_side, checkpoint_stride);
+  if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;
+  StripTable tab = make_table(strips, n_strips);
+  hipError_t err = launch_multiterminal_mfma(tab, probs_dev, P, onsite, sigmaL, sigmaR, CL, CR, n_side, side_dev,
+                                             sigmaX, CX, st, T, pstatus, ws, Mmax, Lmax, (hipStream_t)stream);
+  return err == hipSuccess ? KNIT_OK : KNIT_E_DEVICE;
+}
+
 }  // extern "C"

@@ -105,6 +105,13 @@ hipError_t launch_lesser_mfma(const StripTable &tab, const knit_problem *probs, 
                               knit_z *blk, const int64_t *blk_off, double *jlong, double *jtran, int32_t *pstatus,
                               void *ws, int Mmax, int Lmax, hipStream_t stream);
 
+size_t multiterminal_mfma_workspace(int Mmax, int Lmax, int stride, int n_side, int P);
+hipError_t launch_multiterminal_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                                     const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, const knit_z *CR,
+                                     int n_side, const knit_lead *side, const knit_z *sigmaX, const knit_z *CX,
+                                     int stride, double *T, int32_t *pstatus, void *ws, int Mmax, int Lmax,
+                                     hipStream_t stream);
+
 size_t transmission_eigs_workspace(int Mmax, int P);
 hipError_t launch_transmission_eigs(const StripTable &tab, const knit_problem *probs, int P, int Mmax,
                                     const knit_z *CR, const knit_z *G1Np, int ld, double *tn, int32_t *nch,

@@ -1592,6 +1592,343 @@ lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_
   }
 }
 
+// The reverse coupling of the right-connected recursion, X -= V^+ gR V, for a
+// block-monomial V: site block (b, b') receives vblk[a]^+ gR[a, a'] vblk[a']
+// with a, a' the sites bonded to b, b' (inv = the inverse of vcol, -1 where
+// none).  gR natural order, [Mp][Mp].  One site block per thread.
+template <class RS>
+__device__ void reverse_coupling_blocks(cpx<double> *X, const StripDev &s, const int *inv, const cpx<RS> *gR,
+                                        int Mp) {
+  const int no = s.norb, W = s.M / no;
+  for (int blk = threadIdx.x; blk < W * W; blk += blockDim.x) {
+    const int b = blk / W, b2 = blk % W;
+    const int a = inv[b], a2 = inv[b2];
+    if (a < 0 || a2 < 0) continue;
+    for (int ob = 0; ob < no; ++ob)
+      for (int ob2 = 0; ob2 < no; ++ob2) {
+        cpx<double> acc = {0.0, 0.0};
+        for (int i = 0; i < no; ++i) {
+          cpx<double> inner = {0.0, 0.0};
+          for (int j = 0; j < no; ++j)
+            inner = c_fma(cvt<double>(gR[(int64_t)(a * no + i) * Mp + a2 * no + j]), vblk_at(s, a2, j, ob2), inner);
+          acc = c_fma(c_conj(vblk_at(s, a, i, ob)), inner, acc);
+        }
+        cpx<double> &x = X[(int64_t)(b * no + ob) * Mp + b2 * no + ob2];
+        x = cpx<double>{x.re - acc.re, x.im - acc.im};
+      }
+  }
+}
+
+// Y = Gm V on the first `nrows` rows for a block-monomial V: column block b of Y
+// is column block inv[b] of Gm times vblk[inv[b]] (zero where inv[b] < 0).
+template <class RS>
+__device__ void right_mul_v_blocks(cpx<RS> *Y, const cpx<RS> *Gm, const StripDev &s, const int *inv, int Mp,
+                                   int nrows) {
+  const int M = s.M, no = s.norb;
+  for (int64_t i = threadIdx.x; i < (int64_t)nrows * Mp; i += blockDim.x) {
+    const int r = (int)(i / Mp), c = (int)(i % Mp);
+    cpx<double> acc = {0.0, 0.0};
+    if (c < M) {
+      const int b = c / no, ob = c % no, a = inv[b];
+      if (a >= 0)
+        for (int oa = 0; oa < no; ++oa)
+          acc = c_fma(cvt<double>(Gm[(int64_t)r * Mp + a * no + oa]), vblk_at(s, a, oa, ob), acc);
+    }
+    Y[i] = cvt<RS>(acc);
+  }
+}
+
+constexpr int MT_MAX_LEADS = 8;   // left, right and up to six side leads
+
+// Conductance matrix of a strip with leads on several slices (section 2.3,
+// T_kl = Tr[Gamma_k G_kl Gamma_l G_kl^+]; section 6.1, the conductance matrix),
+// FP64, one workgroup per problem.  Lead 0 is the left lead (slice 0, Sigma_L,
+// C_L), lead 1 the right lead (slice L-1, Sigma_R, C_R), leads 2.. are the side
+// leads of the call (slice, Sigma_k = sigmaX + off, C_k = CX + off), every
+// Gamma_k = C_k C_k^+.  With A_n the local slice matrix (E - H_n minus every
+// self-energy attached to slice n):
+//   forward:  left-connected g^L_n = (A_n - V g^L_{n-1} V^+)^{-1}, checkpoints;
+//   reverse:  right-connected g^R_n = (A_n - V^+ g^R_{n+1} V)^{-1}; at a slice
+//             hosting leads the full block
+//             G_nn = (A_n - V g^L_{n-1} V^+ - V^+ g^R_{n+1} V)^{-1};
+//             each lead l at slice n starts its column Y_l = G_nn C_l and row
+//             R_l = C_l^+ G_nn, which move one slice down per step by Dyson's
+//             equation across the cut (n-1 | n):
+//               Y_l <- g^L_{n-1} V^+ Y_l     (= G_{n-1, s_l} C_l)
+//               R_k <- R_k V g^L_{n-1}       (= C_k^+ G_{s_k, n-1});
+//   T_kl      = || C_k^+ Y_l ||_F^2 when the sweep reaches s_k <= s_l,
+//             = || R_k C_l ||_F^2   when it reaches s_l <  s_k.
+// Slab (Mp^2 elements each): X, U, U2, gRa, gRb, Gnn, C (one lead's factor,
+// padded), Y[K], R[K], the segment's g^L [max(st, 2)], checkpoints
+// [ceil(Lmax / st)], V, V^+, then the elimination scratch.
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+multiterminal_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_z *onsite,
+                          const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, const knit_z *CR,
+                          int n_side, const knit_lead *side, const knit_z *sigmaX, const knit_z *CX, int stride,
+                          double *Tout, int32_t *pstatus, char *ws, size_t slab_bytes, int Mpmax, int Lmax,
+                          unsigned int *queue, const int *order, int outer) {
+  using C = cpx<double>;
+  __shared__ int next_p;
+  __shared__ int q[NT], pinv[NT];
+  __shared__ int vinv[NT];
+  __shared__ double sv[32];
+  __shared__ int si[64];
+  __shared__ C xchg[2 * 32];
+  __shared__ C prow[32];
+  __shared__ int lslice[MT_MAX_LEADS], lrank[MT_MAX_LEADS];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int K = n_side + 2;
+  const int64_t EE = (int64_t)Mpmax * Mpmax;
+  const int segbuf = stride < 2 ? 2 : stride;
+  const int nsegmax = (Lmax + stride - 1) / stride;
+  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  C *X = reinterpret_cast<C *>(slab);
+  C *U = X + EE, *U2 = U + EE, *gRa = U2 + EE, *gRb = gRa + EE, *Gnn = gRb + EE, *Cb = Gnn + EE;
+  C *Yb = Cb + EE;                                  // [K][Mp][Mp]
+  C *Rb = Yb + (int64_t)K * EE;                     // [K][Mp][Mp]
+  C *segg = Rb + (int64_t)K * EE;                   // [segbuf][Mp][Mp]
+  C *cpg = segg + (int64_t)segbuf * EE;             // [nsegmax][Mp][Mp]
+  C *Vd = cpg + (int64_t)nsegmax * EE, *Vh = Vd + EE;
+  C *Sb = Vh + EE;                                  // [2 Mp][NO] scratch
+  C *Sd = Sb + (int64_t)2 * Mpmax * NO_MAX;         // [NO][Mp]   scratch
+  const double qnan = __builtin_nan("");
+  for (;;) {
+    if (tid == 0) next_p = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int pi = next_p;
+    __syncthreads();
+    if (pi >= P) break;
+    const int p = order[pi];
+    const knit_problem pr = probs[p];
+    const StripDev s = tab.s[pr.strip];
+    const int M = s.M, no = s.norb, W = M / no, L = pr.L;
+    const int Mp = (M + MPAD - 1) / MPAD * MPAD;
+    const int64_t E2 = (int64_t)Mp * Mp;
+    const knit_z *sL = sigmaL + pr.sigma_off, *sR = sigmaR + pr.sigma_off;
+    const knit_lead *sd = side + (int64_t)p * n_side;
+    const bool dense = s.V != nullptr;
+    const int nseg = (L + stride - 1) / stride;
+    int flags = 0;
+    // factor of lead k (device, [M][M], row stride M)
+    auto factor = [&](int k) -> const knit_z * {
+      return k == 0 ? CL + pr.sigma_off : (k == 1 ? CR + pr.sigma_off : CX + sd[k - 2].sigma_off);
+    };
+    // lead slices, ranks (columns of C up to the last nonzero one), vcol inverse, V
+    if (tid < K) lslice[tid] = tid == 0 ? 0 : (tid == 1 ? L - 1 : min(max(sd[tid - 2].slice, 0), L - 1));
+    for (int k = 0; k < K; ++k) {
+      const int r = factor_columns(factor(k), M, sv);
+      if (tid == 0) lrank[k] = r < M ? r : M;
+    }
+    if (!dense) {
+      for (int b = tid; b < W; b += nt) vinv[b] = -1;
+      __syncthreads();
+      for (int a = tid; a < W; a += nt)
+        if (s.vcol[a] >= 0) vinv[s.vcol[a]] = a;
+    } else {
+      load_dense_v<double>(Vd, Vh, s, Mp);
+    }
+    __syncthreads();
+    // local slice matrix of slice n into X (natural order): E - H_n - the self-energies
+    // attached to it, plus the forward coupling with gl (g^L_{n-1}, or null) and the
+    // reverse coupling with gr (g^R_{n+1}, or null)
+    auto assemble = [&](int n, const C *gl, const C *gr) {
+      const knit_z *D = onsite + pr.onsite_off + (int64_t)n * s.onsite_stride();
+      form_blocks<double, false, false>(X, nullptr, s, Mp, pr.E, D, sL, sR, n == 0, n == L - 1,
+                                        [=](int rr, int c) { return gl[(int64_t)rr * Mp + c]; },
+                                        [=](int rr, int c) { return C{0.0, 0.0}; }, -1, gl != nullptr && !dense);
+      __syncthreads();
+      for (int k = 2; k < K; ++k) {
+        if (lslice[k] != n) continue;
+        const knit_z *sg = sigmaX + sd[k - 2].sigma_off;
+        for (int64_t i = tid; i < (int64_t)M * M; i += nt) {
+          const int a = (int)(i / M), b = (int)(i % M);
+          const C v = ld_z(sg + i);
+          C &x = X[(int64_t)a * Mp + b];
+          x = C{x.re - v.re, x.im - v.im};
+        }
+        __syncthreads();
+      }
+      if (dense && gl) dense_coupling<double, double, false>(X, nullptr, Vd, Vh, gl, nullptr, U, Mp, 0);
+      if (gr) {
+        if (dense) {
+          // X -= V^+ (gR V)
+          wg_gemm_mfma<double>(Mp, Mp, Mp, gr, Mp, Vd, Mp, [&](int rr, int c, double &re, double &im) {
+            U[(int64_t)rr * Mp + c] = C{re, im};
+          });
+          __syncthreads();
+          wg_gemm_mfma<double>(Mp, Mp, Mp, Vh, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
+            C &x = X[(int64_t)rr * Mp + c];
+            x = C{x.re - re, x.im - im};
+          });
+        } else {
+          reverse_coupling_blocks<double>(X, s, vinv, gr, Mp);
+        }
+        __syncthreads();
+      }
+    };
+    // inverse of the assembled X into dst (natural order)
+    auto invert = [&](C *dst) {
+      flags |= outer == 128 ? gj_two_level<double, NT, 128>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd)
+                            : gj_two_level<double, NT, 64>(X, Mp, Mp, q, xchg, prow, sv, si, Sb, Sd);
+      for (int i = tid; i < Mp; i += nt) pinv[q[i]] = i;
+      __syncthreads();
+      for (int64_t i = tid; i < E2; i += nt) {
+        const int a = (int)(i / Mp), b = (int)(i % Mp);
+        dst[i] = X[(int64_t)q[a] * Mp + pinv[b]];
+      }
+      __syncthreads();
+    };
+    // lead k's factor, padded: Cb[a][c] = C_k[a][c] (cols < rank), or its adjoint
+    auto load_factor = [&](int k, bool adjoint) {
+      const knit_z *Ck = factor(k);
+      const int r = lrank[k];
+      for (int64_t i = tid; i < E2; i += nt) {
+        const int a = (int)(i / Mp), c = (int)(i % Mp);
+        C v = {0.0, 0.0};
+        if (!adjoint && a < M && c < r) v = ld_z(Ck + (int64_t)a * M + c);
+        if (adjoint && c < M && a < r) {
+          const C w = ld_z(Ck + (int64_t)c * M + a);
+          v = C{w.re, -w.im};
+        }
+        Cb[i] = v;
+      }
+      __syncthreads();
+    };
+    auto rp_of = [&](int k) { return (lrank[k] + MPAD - 1) / MPAD * MPAD; };
+    // || A B ||_F^2 with A [ra][Mp] and B [Mp][rb] (both padded)
+    auto frob_product = [&](const C *A, int ra, const C *B, int rb) -> double {
+      double ss = 0.0;
+      wg_gemm_mfma<double>(ra, rb, Mp, A, Mp, B, Mp, [&](int rr, int c, double &re, double &im) {
+        ss += re * re + im * im;
+      });
+      __syncthreads();
+      double t = ss;
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if ((tid & 63) == 0) sv[tid >> 6] = t;
+      __syncthreads();
+      double tot = 0.0;
+      for (int w = 0; w < (nt >> 6); ++w) tot += sv[w];
+      __syncthreads();
+      return tot;
+    };
+    double *Tp = Tout + (int64_t)p * K * K;
+    // ---- forward: left-connected g^L_n, checkpoint k holds g^L of slice k st - 1
+    {
+      C *cur = segg, *prev = segg + E2;
+      for (int n = 0; n < L; ++n) {
+        assemble(n, n > 0 ? prev : nullptr, nullptr);
+        invert(cur);
+        if ((n + 1) % stride == 0 && n + 1 < L) {
+          C *cp = cpg + (int64_t)((n + 1) / stride) * E2;
+          for (int64_t i = tid; i < E2; i += nt) cp[i] = cur[i];
+          __syncthreads();
+        }
+        C *t = cur; cur = prev; prev = t;
+      }
+    }
+    // ---- reverse
+    C *gR = gRa, *gRn = gRb;     // g^R_{n+1} and the one being formed
+    bool have_gR = false;
+    for (int kseg = nseg - 1; kseg >= 0; --kseg) {
+      const int n0 = kseg * stride, n1 = min(L, n0 + stride);
+      // g^L of the segment (slot j holds slice n0 + j)
+      for (int n = n0; n < n1; ++n) {
+        const C *gprev = n == n0 ? (kseg > 0 ? cpg + (int64_t)kseg * E2 : nullptr) : segg + (int64_t)(n - n0 - 1) * E2;
+        assemble(n, n > 0 ? gprev : nullptr, nullptr);
+        invert(segg + (int64_t)(n - n0) * E2);
+      }
+      for (int n = n1 - 1; n >= n0; --n) {
+        const C *gl_prev = n > n0 ? segg + (int64_t)(n - n0 - 1) * E2 : (kseg > 0 ? cpg + (int64_t)kseg * E2 : nullptr);
+        bool here = false;
+        for (int k = 0; k < K; ++k) here = here || lslice[k] == n;
+        if (here) {
+          // full diagonal block and the leads attached here
+          assemble(n, n > 0 ? gl_prev : nullptr, have_gR ? gR : nullptr);
+          invert(Gnn);
+          for (int k = 0; k < K; ++k) {
+            if (lslice[k] != n) continue;
+            const int rp = rp_of(k);
+            load_factor(k, false);
+            wg_gemm_mfma<double>(Mp, rp, Mp, Gnn, Mp, Cb, Mp, [&](int rr, int c, double &re, double &im) {
+              Yb[(int64_t)k * EE + (int64_t)rr * Mp + c] = C{re, im};
+            });
+            __syncthreads();
+            load_factor(k, true);
+            wg_gemm_mfma<double>(rp, Mp, Mp, Cb, Mp, Gnn, Mp, [&](int rr, int c, double &re, double &im) {
+              Rb[(int64_t)k * EE + (int64_t)rr * Mp + c] = C{re, im};
+            });
+            __syncthreads();
+          }
+          // transmissions whose lower slice is n
+          for (int k = 0; k < K; ++k)
+            for (int l = 0; l < K; ++l) {
+              const int sk = lslice[k], sl = lslice[l];
+              if (min(sk, sl) != n) continue;
+              double t;
+              if (sk == n) {                                   // sink here: || C_k^+ Y_l ||^2
+                load_factor(k, true);
+                t = frob_product(Cb, rp_of(k), Yb + (int64_t)l * EE, rp_of(l));
+              } else {                                         // source here, sink above: || R_k C_l ||^2
+                load_factor(l, false);
+                t = frob_product(Rb + (int64_t)k * EE, rp_of(k), Cb, rp_of(l));
+              }
+              if (tid == 0) Tp[k * K + l] = t;
+            }
+        }
+        // right-connected g^R_n for the next slice down (not needed below slice 0)
+        if (n > 0) {
+          assemble(n, nullptr, have_gR ? gR : nullptr);
+          invert(gRn);
+          C *t = gR; gR = gRn; gRn = t;
+          have_gR = true;
+          // move the active columns and rows down to slice n-1 with g^L_{n-1}
+          const C *gl = gl_prev;
+          for (int k = 0; k < K; ++k) {
+            if (lslice[k] < n) continue;
+            const int rp = rp_of(k);
+            C *Y = Yb + (int64_t)k * EE, *R = Rb + (int64_t)k * EE;
+            // Y <- g^L_{n-1} (V^+ Y)
+            if (dense)
+              wg_gemm_mfma<double>(Mp, rp, Mp, Vh, Mp, Y, Mp, [&](int rr, int c, double &re, double &im) {
+                U[(int64_t)rr * Mp + c] = C{re, im};
+              });
+            else
+              scatter_vdag<double>(U, Y, s, Mp, rp);
+            __syncthreads();
+            wg_gemm_mfma<double>(Mp, rp, Mp, gl, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
+              Y[(int64_t)rr * Mp + c] = C{re, im};
+            });
+            __syncthreads();
+            // R <- (R V) g^L_{n-1}
+            if (dense)
+              wg_gemm_mfma<double>(rp, Mp, Mp, R, Mp, Vd, Mp, [&](int rr, int c, double &re, double &im) {
+                U2[(int64_t)rr * Mp + c] = C{re, im};
+              });
+            else
+              right_mul_v_blocks<double>(U2, R, s, vinv, Mp, rp);
+            __syncthreads();
+            wg_gemm_mfma<double>(rp, Mp, Mp, U2, Mp, gl, Mp, [&](int rr, int c, double &re, double &im) {
+              R[(int64_t)rr * Mp + c] = C{re, im};
+            });
+            __syncthreads();
+          }
+        }
+      }
+    }
+    // non-finite check
+    double bad = 0.0;
+    for (int i = tid; i < K * K; i += nt) bad = fmax(bad, fabs(Tp[i]));
+    if (bad != bad) bad = INFINITY;
+    bad = wg_max_nan(bad, sv);
+    if (!(bad <= 1.79e308)) flags |= KNIT_P_NONFINITE;
+    if (flags & (KNIT_P_SINGULAR | KNIT_P_NONFINITE))
+      for (int i = tid; i < K * K; i += nt) Tp[i] = qnan;
+    if (tid == 0) pstatus[p] = flags;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int mfma_padded(int M) { return (M + MPAD - 1) / MPAD * MPAD; }
@@ -1734,6 +2071,53 @@ hipError_t launch_lesser_mfma(const StripTable &tab, const knit_problem *probs, 
     hipLaunchKernelGGL(lesser_mfma_kernel<512>, dim3(grid), dim3(512), 0, stream, tab, probs, P, onsite, sigmaL,
                        sigmaR, CL, (const int *)rows, stride, blk, blk_off, jlong, jtran, pstatus, w, slab, Mpmax,
                        Lmax, queue, order, tune.outer);
+  return hipGetLastError();
+}
+
+size_t multiterminal_mfma_slab_bytes(int Mmax, int Lmax, int stride, int n_side) {
+  const size_t Mp = (size_t)mfma_padded(Mmax);
+  const size_t EE = Mp * Mp;
+  const size_t segbuf = stride < 2 ? 2 : stride;
+  const size_t nseg = (Lmax + stride - 1) / stride;
+  const size_t K = (size_t)n_side + 2;
+  size_t b = (7 + 2 * K + segbuf + nseg + 2) * EE * 16 + (2 * Mp * NO_MAX + NO_MAX * Mp) * 16;
+  return (b + 255) & ~size_t(255);
+}
+
+size_t multiterminal_mfma_workspace(int Mmax, int Lmax, int stride, int n_side, int P) {
+  const int grid = P < SWEEP_MAX_GRID ? P : SWEEP_MAX_GRID;
+  return 256 + order_bytes(P) + multiterminal_mfma_slab_bytes(Mmax, Lmax, stride, n_side) * (size_t)grid;
+}
+
+hipError_t launch_multiterminal_mfma(const StripTable &tab, const knit_problem *probs, int P, const knit_z *onsite,
+                                     const knit_z *sigmaL, const knit_z *sigmaR, const knit_z *CL, const knit_z *CR,
+                                     int n_side, const knit_lead *side, const knit_z *sigmaX, const knit_z *CX,
+                                     int stride, double *T, int32_t *pstatus, void *ws, int Mmax, int Lmax,
+                                     hipStream_t stream) {
+  unsigned int *queue = reinterpret_cast<unsigned int *>(ws);
+  int *order = reinterpret_cast<int *>(reinterpret_cast<char *>(ws) + 256);
+  char *w = reinterpret_cast<char *>(ws) + 256 + order_bytes(P);
+  const int Mpmax = mfma_padded(Mmax);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  const knit_sweep_tuning tune = sweep_tuning_get(KNIT_FP64, Mpmax);
+  const size_t slab = multiterminal_mfma_slab_bytes(Mmax, Lmax, stride, n_side);
+  int grid = tune.wg_per_cu * ncu;
+  if (grid > SWEEP_MAX_GRID) grid = SWEEP_MAX_GRID;
+  if (grid > P) grid = P;
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, stream, tab, probs, P, tune.order, (const int *)nullptr,
+                     order, queue);
+  if (tune.threads == 256)
+    hipLaunchKernelGGL(multiterminal_mfma_kernel<256>, dim3(grid), dim3(256), 0, stream, tab, probs, P, onsite,
+                       sigmaL, sigmaR, CL, CR, n_side, side, sigmaX, CX, stride, T, pstatus, w, slab, Mpmax, Lmax,
+                       queue, order, tune.outer);
+  else
+    hipLaunchKernelGGL(multiterminal_mfma_kernel<512>, dim3(grid), dim3(512), 0, stream, tab, probs, P, onsite,
+                       sigmaL, sigmaR, CL, CR, n_side, side, sigmaX, CX, stride, T, pstatus, w, slab, Mpmax, Lmax,
+                       queue, order, tune.outer);
   return hipGetLastError();
 }
 

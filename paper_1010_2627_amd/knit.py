@@ -88,6 +88,11 @@ _lib.knit_local_observables_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32
 _lib.knit_local_observables.restype = c_i32
 _lib.knit_local_observables.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp,
                                         c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
+_lib.knit_conductance_matrix_workspace.restype = c_sz
+_lib.knit_conductance_matrix_workspace.argtypes = [_SP, c_i32, c_vp, c_i32, c_i32, c_i32]
+_lib.knit_conductance_matrix.restype = c_i32
+_lib.knit_conductance_matrix.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp,
+                                         c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]
 _lib.knit_transmission_projected.restype = c_i32
 _lib.knit_transmission_projected.argtypes = [_SP, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]
 
@@ -112,7 +117,8 @@ EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
             "knit_transmission_projected", "knit_rgf_sweep_noalloc", "knit_transmission_eigenvalues_workspace",
-            "knit_transmission_eigenvalues", "knit_local_observables_workspace", "knit_local_observables"]
+            "knit_transmission_eigenvalues", "knit_local_observables_workspace", "knit_local_observables",
+            "knit_conductance_matrix_workspace", "knit_conductance_matrix"]
 
 
 class KnitError(RuntimeError):
@@ -476,6 +482,38 @@ def knit_local_observables(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, 
                                        _ptr(workspace), workspace.numel(), _stream(stream))
     _check(code, "knit_local_observables")
     return blk, blk_off, jlong, jtran, status[:P]
+
+
+LEAD_DTYPE = np.dtype([("slice", "<i4"), ("reserved", "<i4"), ("sigma_off", "<i8")], align=True)
+assert LEAD_DTYPE.itemsize == 16
+KNIT_MAX_SIDE_LEADS = 6
+
+
+def knit_conductance_matrix(strips, probs: ProblemTable, onsite, sigmaL, sigmaR, CL, CR, side: np.ndarray,
+                            sigmaX=None, CX=None, checkpoint_stride: int = 0, stream=None,
+                            workspace: torch.Tensor | None = None):
+    """Conductance matrix with side leads.  side: host LEAD_DTYPE [P, n_side] (slice, offsets into
+    sigmaX / CX).  Returns (T [P, K, K] float64 with K = n_side + 2, status [P])."""
+    tab = strip_table(strips)
+    dev = onsite.device
+    P = probs.P
+    side = np.ascontiguousarray(side, dtype=LEAD_DTYPE).reshape(P, -1)
+    n_side = side.shape[1]
+    K = n_side + 2
+    side_dev = torch.from_numpy(side.view(np.uint8).reshape(-1).copy()).to(dev) if n_side else None
+    T = torch.empty((max(P, 1), K, K), dtype=torch.float64, device=dev)
+    status = torch.zeros(max(P, 1), dtype=torch.int32, device=dev)
+    wsz = int(_lib.knit_conductance_matrix_workspace(tab, len(strips), _ptr(probs.host), P, n_side,
+                                                     int(checkpoint_stride)))
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+    code = _lib.knit_conductance_matrix(tab, len(strips), _ptr(probs.host), _ptr(probs.dev), P, _ptr(_z(onsite)),
+                                        _ptr(_z(sigmaL)), _ptr(_z(sigmaR)), _ptr(_z(CL)), _ptr(_z(CR)), n_side,
+                                        _ptr(side) if n_side else None, _ptr(side_dev),
+                                        _ptr(sigmaX), _ptr(CX), int(checkpoint_stride), _ptr(T), _ptr(status),
+                                        _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(code, "knit_conductance_matrix")
+    return T[:P], status[:P]
 
 
 def _strip_M(s) -> int:
