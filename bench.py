@@ -45,8 +45,11 @@ TOL_PER_CHANNEL = 1e-6
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "5feff3ebfd31fe92", "bytes": 5.6522e+13,
-           "profile": "profiles/sweep_fp64_c4_hbm_traffic.md"},
+    "c4": {"sha": "24da09d17f4c8485", "bytes": 5.6515e+13,
+           "profile": "profiles/sweep_fp64_c4_hbm_traffic.md",
+           # executed matrix work and L2 behaviour of the same launch (same counter runs)
+           "counters": {"mfma_f64_flops_executed": 4.2922e+14, "mfma_busy_fraction": 0.378,
+                        "l2_hit_rate": 0.493}},
 }
 
 
@@ -423,6 +426,7 @@ def main():
                      "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (calibrated counters)",
                      "traffic_source": tr["profile"] if traffic else None,
+                     "counters": tr["counters"] if traffic else None,
                      "kernel": f"sweep_mfma_kernel<double, double, false, {sweep_threads}, true> (FP64 MFMA, "
                                f"projected)",
                      "flops_per_slice_step": "8*M^3 + 8*M^2*r (inverse + projected propagator, r = rank "
