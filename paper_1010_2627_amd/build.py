@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libknit.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["abi.hip", "decim.hip", "sweep.hip", "sweep_mfma.hip", "trace.hip", "ldos.hip", "mlp.hip", "noalloc.hip", "noise.hip"]
+SOURCES = ["abi.hip", "decim.hip", "sweep.hip", "sweep_mfma.hip", "trace.hip", "ldos.hip", "mlp.hip", "noalloc.hip", "noise.hip", "graph.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

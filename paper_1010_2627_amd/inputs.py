@@ -299,3 +299,111 @@ def general_square_system(sites, t: float = 1.0):
             if j is not None:
                 H[i, j] = H[j, i] = t
     return H, index
+
+
+# ---------------------------------------------------------------- systems of any shape (knitting)
+
+@dataclass
+class Graph:
+    """A tight-binding system of any shape (Eq. (1)): N sites with norb orbitals,
+    a CSR hopping graph (row_ptr, col) with the block H_{i, col[e]} per directed
+    edge e in ``hop`` [nnz, norb, norb], and on-site blocks ``onsite`` [N, norb, norb]."""
+    N: int
+    norb: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    hop: np.ndarray
+    onsite: np.ndarray
+    coords: list | None = None
+
+    def dense(self) -> np.ndarray:
+        """The full [N*norb, N*norb] Hamiltonian."""
+        no = self.norb
+        H = np.zeros((self.N * no, self.N * no), dtype=np.complex128)
+        for i in range(self.N):
+            H[i * no:(i + 1) * no, i * no:(i + 1) * no] = self.onsite[i]
+            for e in range(self.row_ptr[i], self.row_ptr[i + 1]):
+                j = self.col[e]
+                H[i * no:(i + 1) * no, j * no:(j + 1) * no] = self.hop[e]
+        return H
+
+
+def graph_from_blocks(N: int, norb: int, onsite: np.ndarray, bonds: dict) -> Graph:
+    """``bonds`` maps (i, j) to the block H_{ij}; H_{ji} = H_{ij}^+ is added for every bond."""
+    rows = [dict() for _ in range(N)]
+    for (i, j), b in bonds.items():
+        b = np.asarray(b, dtype=np.complex128).reshape(norb, norb)
+        rows[i][j] = b
+        rows[j][i] = b.conj().T
+    row_ptr = np.zeros(N + 1, dtype=np.int32)
+    col, hop = [], []
+    for i in range(N):
+        for j in sorted(rows[i]):
+            col.append(j)
+            hop.append(rows[i][j])
+        row_ptr[i + 1] = len(col)
+    hop = np.array(hop, dtype=np.complex128).reshape(len(col), norb, norb)
+    return Graph(N, norb, row_ptr, np.array(col, dtype=np.int32), hop,
+                 np.asarray(onsite, dtype=np.complex128).reshape(N, norb, norb))
+
+
+def square_lattice_graph(sites, t: float = 1.0, flux: float = 0.0, kind: str = "scalar", mu: float = 0.0,
+                         delta: float = 0.0, alpha: float = 0.0, ez: float = 0.0) -> Graph:
+    """Square-lattice sites (list of integer (x, y)), nearest-neighbour bonds.
+
+    * ``flux``: magnetic flux per plaquette in flux quanta, Landau gauge: the
+      x-bond from (x, y) to (x+1, y) carries the Peierls phase exp(2 pi i flux y).
+    * ``kind``: "scalar" (one orbital, H_ij = -t), "bdg" (electron-hole blocks
+      diag(-t e^{i phi}, +t e^{-i phi}) on bonds, diag(-mu, mu) + delta sigma_x
+      on site), "rashba" (spin-1/2: -t on bonds plus the Rashba term
+      i alpha (sigma_y for x-bonds, -sigma_x for y-bonds), ez sigma_z on site).
+    """
+    index = {tuple(s): i for i, s in enumerate(sites)}
+    N = len(sites)
+    sx = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    sz = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+    no = 1 if kind == "scalar" else 2
+    onsite = np.zeros((N, no, no), dtype=np.complex128)
+    if kind == "bdg":
+        onsite[:] = np.array([[-mu, delta], [delta, mu]], dtype=np.complex128)
+    elif kind == "rashba":
+        onsite[:] = ez * sz
+    bonds = {}
+    for (x, y), i in index.items():
+        for dx, dy in ((1, 0), (0, 1)):
+            j = index.get((x + dx, y + dy))
+            if j is None:
+                continue
+            ph = np.exp(2j * np.pi * flux * y) if dx == 1 else 1.0
+            if kind == "scalar":
+                b = np.array([[-t * ph]])
+            elif kind == "bdg":
+                b = np.array([[-t * ph, 0], [0, t * np.conj(ph)]])
+            else:
+                b = -t * ph * np.eye(2) + 1j * alpha * ph * (sy if dx == 1 else -sx)
+            bonds[(i, j)] = b
+    g = graph_from_blocks(N, no, onsite, bonds)
+    g.coords = [tuple(s) for s in sites]
+    return g
+
+
+def graph_disorder(g: Graph, w: float, seed: int) -> np.ndarray:
+    """On-site blocks [N, norb, norb] of g plus eps * identity, eps ~ U[-w/2, w/2], PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps = w * (rng.random(g.N) - 0.5)
+    out = g.onsite.copy()
+    for i in range(g.N):
+        out[i] += eps[i] * np.eye(g.norb)
+    return out
+
+
+def rectangle_with_hole(Lx: int, Ly: int, hole: tuple | None = None):
+    """Sites of an Lx x Ly rectangle, minus the rectangle hole = (x0, y0, x1, y1) (inclusive)."""
+    sites = []
+    for x in range(Lx):
+        for y in range(Ly):
+            if hole and hole[0] <= x <= hole[2] and hole[1] <= y <= hole[3]:
+                continue
+            sites.append((x, y))
+    return sites

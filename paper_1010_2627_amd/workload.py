@@ -249,3 +249,44 @@ def uneven_batch(n_strips=512, n_energies=32, emin=-3.9, emax=3.9, device="cuda"
                                                         int(lay.seeds[i])), f"strip{i}"))
     E = inputs.midpoint_grid(emin, emax, n_energies)
     return Batch(strips, reals, [E for _ in strips], device)
+
+
+# ---------------------------------------------------------------- systems of any shape
+
+class GraphBatch:
+    """Problems of one system of any shape (``inputs.Graph``) and its leads, resident
+    on the GPU: energies, per-realization on-site blocks and per-problem self-energy
+    packs (lead k's Sigma_k [n_k norb]^2 after the earlier leads').  Arranges arrays
+    only; the knitting runs in ``knit_graph_transmission``."""
+
+    def __init__(self, g, leads, energies, onsites, sigmas, device="cuda", order=None):
+        from . import graph as GR
+        self.g, self.leads = g, [np.asarray(l, dtype=np.int32) for l in leads]
+        self.plan = GR.plan_create(g.N, g.norb, g.row_ptr, g.col, self.leads, order)
+        self.info = self.plan.info()
+        E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+        P = len(E)
+        onsites = np.asarray(onsites, dtype=np.complex128).reshape(-1, g.N, g.norb, g.norb)
+        real_of = np.arange(P) % onsites.shape[0] if onsites.shape[0] > 1 else np.zeros(P, dtype=np.int64)
+        ss = self.info["sigma_size"]
+        packs = np.zeros((P, ss), dtype=np.complex128)
+        for p in range(P):
+            o = 0
+            for k in range(len(self.leads)):
+                s = np.asarray(sigmas[k][p], dtype=np.complex128)
+                packs[p, o:o + s.size] = s.ravel()
+                o += s.size
+            assert o == ss
+        ld = self.info["lead_dim"]
+        tab = GR.problem_table(E, real_of * g.N * g.norb * g.norb, np.arange(P) * ss, np.arange(P) * ld * ld)
+        self.P, self.E, self.real_of = P, E, real_of
+        self.device = device
+        self.hop = torch.from_numpy(np.ascontiguousarray(g.hop)).to(device) if len(g.col) else None
+        self.onsite = torch.from_numpy(np.ascontiguousarray(onsites)).to(device)
+        self.sigma = torch.from_numpy(packs).to(device)
+        self.probs = torch.from_numpy(tab.view(np.uint8).copy()).to(device)
+
+    def run(self, want_gll=False, stream=None):
+        from . import graph as GR
+        return GR.knit_graph_transmission(self.plan, self.probs, self.P, self.hop, self.onsite, self.sigma,
+                                          want_gll=want_gll, stream=stream)
