@@ -233,6 +233,55 @@ def _cpu_baseline(cfg, b, budget_s=20.0, n_energies=None):
             "sample": f"{nE} energies x 1 seed of this workload, first {Ls} of {L} slices; {what}"}
 
 
+# Knitting of a system of any shape (site by site): a 56 x 256 square-lattice sample with a
+# 64 x 16 hole, magnetic flux 0.01 per plaquette, disorder U[-0.5, 0.5], two end leads and a
+# 12-site lead on the top edge; 512 energies.  The interface matrix (dimension <= 128) lives in
+# registers; the kernel's work is the rank-1 update of that matrix per added site.
+GRAPH_WORKLOAD = dict(W=56, L=256, hole=(96, 20, 159, 35), flux=0.01, w=1.0, top=(120, 132), P=512,
+                      desc="square-lattice sample 56 x 256 with a 64 x 16 hole, flux 0.01 per plaquette, "
+                           "disorder U[-0.5,0.5], leads on both ends and 12 top-edge sites, 512 energies, "
+                           "seeded synthetic lead self-energies")
+
+
+def graph_leg(steps=3):
+    import torch
+    from paper_1010_2627_amd import inputs, workload
+    c = GRAPH_WORKLOAD
+    W, L = c["W"], c["L"]
+    g = inputs.square_lattice_graph(inputs.rectangle_with_hole(L, W, c["hole"]), flux=c["flux"])
+    idx = {s: i for i, s in enumerate(g.coords)}
+    leads = [[idx[(0, y)] for y in range(W)], [idx[(L - 1, y)] for y in range(W)],
+             [idx[(x, W - 1)] for x in range(*c["top"])]]
+    P = c["P"]
+    E = inputs.midpoint_grid(-3.5, 3.5, P)
+    sig = [inputs.synthetic_sigma(len(l), P, seed=2101 + k, rank=max(1, len(l) // 2)) for k, l in enumerate(leads)]
+    b = workload.GraphBatch(g, leads, E, inputs.graph_disorder(g, c["w"], seed=10102627), sig)
+    inf = b.info
+    ws = torch.empty(b.plan.workspace(P), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    T, _, st = b.run(ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        T, _, st = b.run(ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / steps
+    flops = inf["update_flops"] * P
+    Tn = T.cpu().numpy()
+    return {"workload": c["desc"], "sites": inf["nsite"], "norb": inf["norb"], "leads": len(leads),
+            "interface_dim_max": inf["dim"], "site_steps_per_launch": inf["n_steps"] * P,
+            "seconds_per_launch": round(t, 5), "site_steps_per_s": inf["n_steps"] * P / t,
+            "t_matrices_per_s": P / t, "problems_with_status": int((st.cpu().numpy() != 0).sum()),
+            "row_sum_check_max": float(np.abs(Tn[:, 0, 1:].sum(axis=1) - Tn[:, 1:, 0].sum(axis=1)).max()),
+            "roofline": {"bound": "alu", "achieved": flops / t / 1e12, "peak": PEAK_TFLOPS["fp64"],
+                         "unit": "TFLOP/s", "frac": flops / t / 1e12 / PEAK_TFLOPS["fp64"],
+                         "kernel": "graph_knit_kernel<512, 8, 4, true, 1> (interface matrix in registers)",
+                         "flops_per_launch": flops,
+                         "flops_per_site_step": "8 norb D_t^2 (rank-norb update of the interface matrix)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,6 +526,9 @@ def main():
         out["ldos"] = ldos_info
     if tuning is not None:
         out["autotune"] = tuning
+    if not args.headline_only:
+        out["graph_knitting"] = graph_leg()
+        progress("graph knitting done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, b)
         progress("cpu baseline done")

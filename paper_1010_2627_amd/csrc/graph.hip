@@ -54,7 +54,7 @@ using Z = cpx<double>;
 
 // word offsets in the plan image header
 enum {
-  H_N, H_M, H_K, H_N0, H_NSTEPS, H_DIM, H_LDIM, H_LEADOFF, H_LSLOT, H_LSITE, H_INIT, H_STEPOFF, H_STEPS,
+  H_N, H_M, H_K, H_N0, H_NSTEPS, H_DIM, H_LDIM, H_LEADOFF, H_LSLOT, H_LSITE, H_INIT, H_REC, H_STEPS,
   H_NLS, H_WORDS = 16
 };
 
@@ -258,6 +258,9 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
   __shared__ Z sf[REG ? DM : 1];
   __shared__ Z hr[NPAIR][MMAX], hc[NPAIR][MMAX], gsh[MMAX][MMAX];
   __shared__ int pcol[NPAIR];
+  // register mode: step records and coupling blocks, double-buffered
+  __shared__ int srec[4][REG ? 4 + 3 * NPAIR : 1], spcol[2][REG ? NPAIR : 1];
+  __shared__ Z shr[2][REG ? NPAIR : 1][M], shc[2][REG ? NPAIR : 1][M], shii[2][M * M];
   __shared__ double sv[NT / WAVE];
   __shared__ int si[NT / WAVE];
   __shared__ int sflag;
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
   const int32_t *lslot = img + img[H_LSLOT];       // slot of every lead site, lead order
   const int32_t *lsite = img + img[H_LSITE];       // site of every lead site
   const int32_t *init = img + img[H_INIT];         // count, then (a, b, e) per hop inside lead 0
-  const int32_t *stepoff = img + img[H_STEPOFF];
+  const int R = img[H_REC];                         // words per step record
   const int32_t *steps = img + img[H_STEPS];
   const int mm = m * m;
   (void)N;
@@ -339,25 +342,47 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
     __syncthreads();
 
     // ---- 2. the sites one at a time
-    for (int t = 0; t < nsteps; ++t) {
-      const int32_t *st = steps + stepoff[t];
-      const int site = st[0], sl = st[1], Da = st[2], nent = st[3];
-      const int np = nent * m;
-      // phase 1: coupling blocks, and (register mode) the owners stage the coupled columns and rows
-      if (tid < np) {
-        const int j = tid, en = j / m, q = j % m;
-        const int slot = st[4 + 3 * en], erow = st[5 + 3 * en], ecol = st[6 + 3 * en];
-        pcol[j] = slot * m + q;
-        for (int k = 0; k < m; ++k) {
-          hr[j][k] = ldz(hop + (int64_t)erow * mm + k * m + q);   // H_{i,nb}[k][q]
-          hc[j][k] = ldz(hop + (int64_t)ecol * mm + q * m + k);   // H_{nb,i}[q][k]
-        }
+    if constexpr (REG) {
+      // Two barriers per step.  Step t's record sits in LDS slot t & 3 and its
+      // coupling blocks in buffer t & 1; the record of step t+3 and the blocks
+      // of step t+1 are loaded into registers at the top of step t and stored
+      // at its end, so their latency hides behind the step.
+      for (int e = tid; e < 3 * R; e += NT) {
+        const int tt = e / R;
+        srec[tt][e % R] = tt < nsteps ? steps[(int64_t)tt * R + e % R] : 0;
       }
-      if constexpr (REG) {
-        // every register is addressed statically: each column (row) of the
-        // thread's tile is compared with the coupled orbitals
+      __syncthreads();
+      if (nsteps > 0) {
+        const int nent0 = srec[0][3];
+        for (int e = tid; e < nent0 * mm; e += NT) {
+          const int j = e / M, k = e % M, en = j / M, q = j % M;
+          shr[0][j][k] = ldz(hop + (int64_t)srec[0][5 + 3 * en] * mm + k * M + q);
+          shc[0][j][k] = ldz(hop + (int64_t)srec[0][6 + 3 * en] * mm + q * M + k);
+        }
+        if (tid < mm) shii[0][tid] = ldz(ons + (int64_t)srec[0][0] * mm + tid);
+      }
+      __syncthreads();
+      for (int t = 0; t < nsteps; ++t) {
+        const int cur = t & 1, nxt = cur ^ 1, rc = t & 3, rn = (t + 1) & 3;
+        const int sl = srec[rc][1], Da = srec[rc][2], nent = srec[rc][3];
+        const int np = nent * M;
+        // prefetch: record t+3, blocks of step t+1
+        const bool has1 = t + 1 < nsteps, has3 = t + 3 < nsteps;
+        int recv = 0;
+        if (has3 && tid < R) recv = steps[(int64_t)(t + 3) * R + tid];
+        const int nent1 = has1 ? srec[rn][3] : 0;
+        Z phr = {0.0, 0.0}, phc = {0.0, 0.0}, phii = {0.0, 0.0};
+        if (tid < nent1 * mm) {
+          const int j = tid / M, k = tid % M, en = j / M, q = j % M;
+          phr = ldz(hop + (int64_t)srec[rn][5 + 3 * en] * mm + k * M + q);
+          phc = ldz(hop + (int64_t)srec[rn][6 + 3 * en] * mm + q * M + k);
+        }
+        if (has1 && tid < mm) phii = ldz(ons + (int64_t)srec[rn][0] * mm + tid);
+        // phase 1: the owners stage the coupled columns and rows; every register
+        // is addressed statically
+        if (tid < np) spcol[cur][tid] = srec[rc][4 + 3 * (tid / M)] * M + tid % M;
         for (int j = 0; j < np; ++j) {
-          const int cj = st[4 + 3 * (j / m)] * m + j % m;
+          const int cj = srec[rc][4 + 3 * (j / M)] * M + j % M;
 #pragma unroll
           for (int b = 0; b < CPT; ++b)
             if (tc + TC * b == cj)
@@ -369,81 +394,166 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
 #pragma unroll
               for (int b = 0; b < CPT; ++b) Gr[j][tc + TC * b] = G.x[a][b];
         }
-      }
-      __syncthreads();
-      // phase 2: u = G[:, nb] H_{nb,i} (D x m), v = H_{i,nb} G[nb, :] (m x D, into w)
-      for (int e = tid; e < Da * m; e += NT) {
-        const int r = e / m, k = e % m;
-        Z s = {0.0, 0.0};
-        for (int j = 0; j < np; ++j) {
-          const Z gv = REG ? Gc[j][r] : SG[(int64_t)r * D + pcol[j]];
-          s = c_fma(gv, hc[j][k], s);
-        }
-        bf.u[r * MMAX + k] = s;
-      }
-      for (int e = tid; e < Da * m; e += NT) {
-        const int k = e / Da, c = e % Da;
-        Z s = {0.0, 0.0};
-        for (int j = 0; j < np; ++j) {
-          const Z gv = REG ? Gr[j][c] : SG[(int64_t)pcol[j] * D + c];
-          s = c_fma(hr[j][k], gv, s);
-        }
-        bf.w[k * bf.ldw + c] = s;
-      }
-      __syncthreads();
-      // phase 3: g = (E - H_ii - H_{i,nb} u[nb])^{-1}
-      step_inverse<M>(np, pcol, hr, bf.u, ons + (int64_t)site * mm, pr.E, gsh, &sflag);
-      __syncthreads();
-      // phase 4: w = g v (per column), ug = u g (per row)
-      for (int c = tid; c < Da; c += NT) {
-        Z v[MMAX];
+        __syncthreads();
+        // every thread: g = (E - H_ii - H_{i,nb} G[nb, nb] H_{nb,i})^{-1} from the
+        // staged columns (G[nb, nb] are their rows pcol)
+        Z g[M][M];
+        {
+          Z a[M][M];
 #pragma unroll
-        for (int k = 0; k < MMAX; ++k) v[k] = k < m ? bf.w[k * bf.ldw + c] : Z{0.0, 0.0};
+          for (int k = 0; k < M; ++k)
 #pragma unroll
-        for (int k = 0; k < MMAX; ++k) {
-          if (k >= m) break;
-          Z s = {0.0, 0.0};
+            for (int l = 0; l < M; ++l) {
+              const Z h = shii[cur][k * M + l];
+              a[k][l] = Z{(k == l ? pr.E : 0.0) - h.re, -h.im};
+            }
+          for (int j = 0; j < np; ++j) {
+            const int r = spcol[cur][j];
+            Z ul[M];
 #pragma unroll
-          for (int l = 0; l < MMAX; ++l)
-            if (l < m) s = c_fma(gsh[k][l], v[l], s);
-          bf.w[k * bf.ldw + c] = s;
+            for (int l = 0; l < M; ++l) ul[l] = Z{0.0, 0.0};
+            for (int i = 0; i < np; ++i) {
+              const Z gv = Gc[i][r];
+#pragma unroll
+              for (int l = 0; l < M; ++l) ul[l] = c_fma(gv, shc[cur][i][l], ul[l]);
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k)
+#pragma unroll
+              for (int l = 0; l < M; ++l) a[k][l] = c_fms(shr[cur][j][k], ul[l], a[k][l]);
+          }
+          if (small_inverse<M>(a, g) && tid == 0) sflag |= KNIT_P_SINGULAR;
         }
-      }
-      for (int r = tid; r < Da; r += NT)
-        for (int k = 0; k < m; ++k) {
-          Z s = {0.0, 0.0};
-          for (int l = 0; l < m; ++l) s = c_fma(bf.u[r * MMAX + l], gsh[l][k], s);
-          bf.ug[r * MMAX + k] = s;
+        // phase 2: u = G[:, nb] H_{nb,i} (D x m), w = g H_{i,nb} G[nb, :] (m x D)
+        for (int e = tid; e < Da * M; e += NT) {
+          const int r = e / M, k = e % M;
+          Z sum = {0.0, 0.0};
+          for (int j = 0; j < np; ++j) sum = c_fma(Gc[j][r], shc[cur][j][k], sum);
+          su[r * MMAX + k] = sum;
         }
-      __syncthreads();
-      // phase 5: G += u w outside the new slot; the new slot's rows and columns
-      const int s0 = sl * m;
-      if constexpr (REG) {
+        for (int c = tid; c < Da; c += NT) {
+          Z v[M];
+#pragma unroll
+          for (int l = 0; l < M; ++l) v[l] = Z{0.0, 0.0};
+          for (int j = 0; j < np; ++j) {
+            const Z gv = Gr[j][c];
+#pragma unroll
+            for (int l = 0; l < M; ++l) v[l] = c_fma(shr[cur][j][l], gv, v[l]);
+          }
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            Z sum = {0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < M; ++l) sum = c_fma(g[k][l], v[l], sum);
+            sw[k * DM + c] = sum;
+          }
+        }
+        __syncthreads();
+        // phase 3: G += u w outside the new slot, G[:, s] = u g, G[s, :] = w, G[s, s] = g
+        const int s0 = sl * M;
+        Z wc[CPT][M];   // w on the thread's columns
+#pragma unroll
+        for (int b = 0; b < CPT; ++b)
+#pragma unroll
+          for (int k = 0; k < M; ++k) wc[b][k] = sw[k * DM + tc + TC * b];   // inside the LDS array
 #pragma unroll
         for (int a = 0; a < RPT; ++a) {
           const int r = tr + 16 * a;
           const bool rin = r < Da, rs = r >= s0 && r < s0 + M;
           Z ur[M];
 #pragma unroll
-          for (int k = 0; k < M; ++k) ur[k] = bf.u[r * MMAX + k];   // r < DM: inside the LDS array
+          for (int k = 0; k < M; ++k) ur[k] = su[r * MMAX + k];
 #pragma unroll
           for (int b = 0; b < CPT; ++b) {
             const int c = tc + TC * b;
             if (rin && c < Da) {
               const bool cs = c >= s0 && c < s0 + M;
               Z x = G.x[a][b];
-              if (rs && cs) x = gsh[r - s0][c - s0];
-              else if (rs) x = bf.w[(r - s0) * bf.ldw + c];
-              else if (cs) x = bf.ug[r * MMAX + c - s0];
-              else {
+              if (rs || cs) {
+                x = Z{0.0, 0.0};
 #pragma unroll
-                for (int k = 0; k < M; ++k) x = c_fma(ur[k], bf.w[k * bf.ldw + c], x);
+                for (int k = 0; k < M; ++k)
+#pragma unroll
+                  for (int l = 0; l < M; ++l) {
+                    if (rs && cs) {
+                      if (r - s0 == k && c - s0 == l) x = g[k][l];
+                    } else if (rs) {
+                      if (r - s0 == k && l == 0) x = wc[b][k];
+                    } else {   // cs: (u g)[r][c - s0]
+                      if (c - s0 == l) x = c_fma(ur[k], g[k][l], x);
+                    }
+                  }
+              } else {
+#pragma unroll
+                for (int k = 0; k < M; ++k) x = c_fma(ur[k], wc[b][k], x);
               }
               G.x[a][b] = x;
             }
           }
         }
-      } else {
+        // the prefetched record and blocks (their slots are no longer read by any
+        // thread: record t-1's slot, step t-1's blocks)
+        if (has3 && tid < R) srec[(t + 3) & 3][tid] = recv;
+        if (tid < nent1 * mm) {
+          shr[nxt][tid / M][tid % M] = phr;
+          shc[nxt][tid / M][tid % M] = phc;
+        }
+        if (has1 && tid < mm) shii[nxt][tid] = phii;
+      }
+    } else {
+      for (int t = 0; t < nsteps; ++t) {
+        const int32_t *st = steps + (int64_t)t * R;
+        const int site = st[0], sl = st[1], Da = st[2], nent = st[3];
+        const int np = nent * m;
+        if (tid < np) {
+          const int j = tid, en = j / m, q = j % m;
+          const int slot = st[4 + 3 * en], erow = st[5 + 3 * en], ecol = st[6 + 3 * en];
+          pcol[j] = slot * m + q;
+          for (int k = 0; k < m; ++k) {
+            hr[j][k] = ldz(hop + (int64_t)erow * mm + k * m + q);   // H_{i,nb}[k][q]
+            hc[j][k] = ldz(hop + (int64_t)ecol * mm + q * m + k);   // H_{nb,i}[q][k]
+          }
+        }
+        __syncthreads();
+        // u = G[:, nb] H_{nb,i} (D x m), v = H_{i,nb} G[nb, :] (m x D, into w)
+        for (int e = tid; e < Da * m; e += NT) {
+          const int r = e / m, k = e % m;
+          Z sum = {0.0, 0.0};
+          for (int j = 0; j < np; ++j) sum = c_fma(SG[(int64_t)r * D + pcol[j]], hc[j][k], sum);
+          bf.u[r * MMAX + k] = sum;
+        }
+        for (int e = tid; e < Da * m; e += NT) {
+          const int k = e / Da, c = e % Da;
+          Z sum = {0.0, 0.0};
+          for (int j = 0; j < np; ++j) sum = c_fma(hr[j][k], SG[(int64_t)pcol[j] * D + c], sum);
+          bf.w[k * bf.ldw + c] = sum;
+        }
+        __syncthreads();
+        step_inverse<M>(np, pcol, hr, bf.u, ons + (int64_t)site * mm, pr.E, gsh, &sflag);
+        __syncthreads();
+        // w = g v (per column), ug = u g (per row)
+        for (int c = tid; c < Da; c += NT) {
+          Z v[M];
+#pragma unroll
+          for (int k = 0; k < M; ++k) v[k] = bf.w[k * bf.ldw + c];
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            Z sum = {0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < M; ++l) sum = c_fma(gsh[k][l], v[l], sum);
+            bf.w[k * bf.ldw + c] = sum;
+          }
+        }
+        for (int r = tid; r < Da; r += NT)
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            Z sum = {0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < M; ++l) sum = c_fma(bf.u[r * MMAX + l], gsh[l][k], sum);
+            bf.ug[r * MMAX + k] = sum;
+          }
+        __syncthreads();
+        const int s0 = sl * m;
         for (int64_t e = tid; e < (int64_t)Da * Da; e += NT) {
           const int r = (int)(e / Da), c = (int)(e % Da);
           const bool rs = r >= s0 && r < s0 + m, cs = c >= s0 && c < s0 + m;
@@ -452,11 +562,13 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
           else if (rs) x = bf.w[(r - s0) * bf.ldw + c];
           else if (cs) x = bf.ug[r * MMAX + c - s0];
           else {
-            Z s = x;
-            for (int k = 0; k < m; ++k) s = c_fma(bf.u[r * MMAX + k], bf.w[k * bf.ldw + c], s);
-            x = s;
+            Z sum = x;
+#pragma unroll
+            for (int k = 0; k < M; ++k) sum = c_fma(bf.u[r * MMAX + k], bf.w[k * bf.ldw + c], sum);
+            x = sum;
           }
         }
+        __syncthreads();
       }
     }
 
@@ -776,10 +888,16 @@ extern "C" int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t
     img.push_back((int32_t)(tri.size() / 3));
     img.insert(img.end(), tri.begin(), tri.end());
   }
-  img[H_STEPOFF] = (int32_t)img.size();
-  img.insert(img.end(), stepoff.begin(), stepoff.end());
+  // fixed-size step records (site, slot, D_t, n, then n x (slot, edge i->j, edge j->i)),
+  // so that a workgroup can fetch any step's record without an index
+  const int R = 4 + 3 * std::max(1, max_pairs / m);
+  img[H_REC] = R;
   img[H_STEPS] = (int32_t)img.size();
-  img.insert(img.end(), steps.begin(), steps.end());
+  for (size_t t = 0; t + 1 < stepoff.size(); ++t) {
+    const size_t n = stepoff[t + 1] - stepoff[t];
+    img.insert(img.end(), steps.begin() + stepoff[t], steps.begin() + stepoff[t + 1]);
+    img.insert(img.end(), R - n, 0);
+  }
 
   knit_graph_info &in = pl->info;
   in.nsite = N;

@@ -286,7 +286,7 @@ class GraphBatch:
         self.sigma = torch.from_numpy(packs).to(device)
         self.probs = torch.from_numpy(tab.view(np.uint8).copy()).to(device)
 
-    def run(self, want_gll=False, stream=None):
+    def run(self, want_gll=False, ws=None, stream=None):
         from . import graph as GR
         return GR.knit_graph_transmission(self.plan, self.probs, self.P, self.hop, self.onsite, self.sigma,
-                                          want_gll=want_gll, stream=stream)
+                                          want_gll=want_gll, ws=ws, stream=stream)
