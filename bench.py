@@ -73,11 +73,12 @@ WORKLOADS = {
                         "64 energies x 8 seeds = 512 problems"),
     "c1": dict(kind="square", W=16, L=64, w=1.0, n_energies=64, n_seeds=1,
                desc="square-lattice strip W=16, L=64, disorder U[-0.5,0.5], 64 energies"),
-    "c5": dict(kind="sampler", Nz=100, L=1024, w=0.6, n_test=4, n_train=128, train_L=(64, 128, 256),
-               train_w=(0.2, 0.8), steps=1500,
+    "c5": dict(kind="sampler", Nz=100, L=1024, w=0.6, n_test=8, n_train=128, train_L=(64, 128, 256),
+               train_w=(0.2, 0.8), steps=1500, n_dense=1024,
                desc="learned energy sampling on a zigzag ribbon (slice dim 200, L=1024, disorder U[-0.3,0.3]): "
                     "network trained by the library's BF16 kernels on 128 ribbons of the same width "
-                    "(L in {64,128,256}, w in [0.2,0.8]); 256 points vs 256 uniform, judged by 4096 points"),
+                    "(L in {64,128,256}, w in [0.2,0.8], targets from 1024 points per curve); 256 points vs 256 "
+                    "uniform on 8 held-out ribbons, judged by 4096 points"),
     "c3": dict(kind="uneven", n_strips=512, n_energies=32,
                desc="uneven batch in one persistent launch: 512 square-lattice strips, W ~ U{32,64,..,256}, "
                     "L ~ U[256,2048], disorder U[-w/2,w/2] with w ~ U[0.5,3], 32 midpoint energies in "
@@ -124,7 +125,8 @@ def sampler_bench(args, cfg):
     from paper_1010_2627_amd import inputs, mlp, sampler as S
     t0 = time.perf_counter()
     X, Q, _ = S.generate_training_set(cfg["n_train"], Nz_choices=(cfg["Nz"],), L_choices=cfg["train_L"],
-                                      w_range=cfg["train_w"], chunk=16, progress=progress)
+                                      w_range=cfg["train_w"], chunk=16, progress=progress,
+                                      n_dense=cfg.get("n_dense", S.N_DENSE))
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     progress(f"training set: {cfg['n_train']} curves in {t_data:.1f} s")
@@ -137,7 +139,7 @@ def sampler_bench(args, cfg):
     progress(f"trained: KL {hist[0][1] - H:.4f} -> {hist[-1][1] - H:.4f} in {t_train:.1f} s")
     test = [S.Ribbon(cfg["Nz"], cfg["L"], cfg["w"], inputs.SEED_BASE + r) for r in range(cfg["n_test"])]
     t2 = time.perf_counter()
-    rows = S.evaluate(net, test, progress=progress)
+    rows = S.evaluate(net, test, progress=progress, chunk=2)
     torch.cuda.synchronize()
     t_eval = time.perf_counter() - t2
     n_points = cfg["n_test"] * (S.N_PROBE + S.N_TOTAL + S.N_JUDGE + 2 + 2 * S.N_LEARNED)

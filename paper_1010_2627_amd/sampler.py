@@ -13,18 +13,34 @@ every proposed point; nothing is interpolated from the network.
 2. **Features.** Probe T / Nmax, the lead's N_open / Nmax at the 512 bin
    centres (a clean-lead property that locates the channel thresholds), log L / 8,
    w and M / 256 (579 numbers; Nmax = max(1, max N_open)).
-3. **Density.** The network outputs a softmax density p over 512 equal bins.
-4. **Placement.** The 192 further energies sit at the deterministic quantiles
-   (j + 1/2)/192 of 0.8·p + 0.2·uniform, linear inside a bin.
+3. **Density.** The network outputs a softmax density p over 512 equal bins:
+   its estimate of where the 256-point trapezoid rule leaves its error.
+4. **Placement.** The placement density is d = 0.8·norm(√p) + 0.2·uniform.
+   The 192 further energies are shared among the 65 intervals that the probe
+   points cut (EMIN, the 64 probe energies, EMAX) in proportion to each
+   interval's mass of d (largest remainders), and sit evenly spaced inside
+   their interval.  A uniform p gives back the evenly spaced 256-point grid
+   (three points between neighbouring probe points), so the probe is never
+   wasted on an uneven grid.
 5. **Integration.** The integrated conductance uses the trapezoid over the
    sorted 256 points, with the interval's end points (T evaluated there too).
 6. **Fallback.** A dense uniform grid is the fallback when p is not finite,
    and a 4096-point one is the judge.
 
-**Training target.** The training target for a curve computed on the dense
-512-point grid is q_j ∝ (|T''_j| + ε)^{1/3}: the trapezoid's local error on a
-step h is about h³|T''|/12, and spacing h ∝ |T''|^{-1/3} equalises it. The
-loss is the cross-entropy of softmax(logits) against q, minimised with AdamW.
+**Training target.** A disordered ribbon's T(E) fluctuates on energy scales
+below the 256-point spacing, so the trapezoid error of each interval behaves
+like a random term whose variance depends on where the interval sits (channel
+thresholds, the edge-state band, resonance-rich stretches).  The error of the
+sum is smallest when the sampling density follows the square root of that
+variance (Neyman's allocation: with n_i points in a stretch of error variance
+s_i² per point, sum s_i²/n_i under sum n_i = n is minimal at n_i ∝ s_i).  So
+the target q of a training curve, computed on a dense grid, is the squared
+signed error of each interval of the uniform 256-point rule, spread over the
+bins it covers, plus a floor of 1e-3 of its mean, normalised; the network's
+softmax fitted by cross-entropy estimates the expected profile given the
+features, and the placement takes its square root.  (Equidistributing the
+curvature, |T''|^{1/3}, is the rule for smooth integrands and loses here.)
+The loss is minimised with AdamW.
 
 **Seeds.** Training curve i uses seed 20101010 + i for its (Nz, L, w) draw and
 its disorder. Evaluation ribbons use 10102627 + r.
@@ -45,6 +61,7 @@ N_BINS = 512
 N_LEARNED = 192
 N_TOTAL = N_PROBE + N_LEARNED
 N_JUDGE = 4096
+N_DENSE = 4096      # dense grid of the training curves (a multiple of N_TOTAL and N_BINS)
 SEED_TRAIN = 20101010
 N_FEATURES = N_PROBE + N_BINS + 3
 SIZES = [N_FEATURES, 256, 256, 256, N_BINS]
@@ -95,10 +112,20 @@ def transmission_curves(ribbons, energies_list, chunk=64, device="cuda", progres
             reals.append(workload.Realization(cls_of[r.Nz], inputs.onsite_disorder(st, r.L, r.w, r.seed)))
         b = workload.Batch(strips, reals, E_cls, device)
         b.compute_sigmas()
+        if int((b.sigma_status.cpu().numpy() != 0).sum()):
+            if b.repair_sigmas():
+                b.repair_sigmas(nudge=1e-6)     # energies exactly on a threshold
         G1N, _, _, status = b.sweep("fp64", gnn=False)
         T = b.transmission(G1N)[0].cpu().numpy()
-        if int((status.cpu().numpy() != 0).sum()) or int((b.sigma_status.cpu().numpy() != 0).sum()):
-            raise RuntimeError("transport path reported a problem status while sampling")
+        st_sig, st_sw = b.sigma_status.cpu().numpy(), status.cpu().numpy()
+        if int((st_sw != 0).sum()) or int((st_sig != 0).sum()):
+            bad = np.nonzero(st_sig != 0)[0]
+            Eall = np.concatenate([np.asarray(e) for e in E_cls])
+            Nall = np.concatenate([np.full(len(e), nz) for e, nz in zip(E_cls, classes)])
+            raise RuntimeError(f"transport path reported a problem status while sampling: {len(bad)} self-energies "
+                               f"at (E, Nz) {[(float(Eall[k]), int(Nall[k])) for k in bad[:8]]} "
+                               f"(status {sorted(set(st_sig[bad].tolist()))}), "
+                               f"{int((st_sw != 0).sum())} sweeps (status {sorted(set(st_sw[st_sw != 0].tolist()))})")
         for ri, i in enumerate(idx):
             E_c = E_cls[cls_of[ribbons[i].Nz]]
             sel = np.searchsorted(E_c, np.asarray(energies_list[i]))
@@ -138,33 +165,56 @@ def features(ribbons, T_probe, nopen_dense):
     return X
 
 
-def target_density(T_dense, eps_rel=1e-2):
-    """q over the N_BINS dense points: (|T''| + eps)^(1/3), normalised (eps = eps_rel * mean|T''|)."""
+def target_density(T_dense, floor_rel=1e-3):
+    """q over the N_BINS bins from a curve on a dense midpoint grid of n points (n a multiple
+    of N_TOTAL and N_BINS): the squared trapezoid error of each interval of the uniform
+    N_TOTAL-point rule, spread over the dense points it covers, averaged per bin, plus a floor
+    of floor_rel times its mean, normalised."""
     T = np.asarray(T_dense, dtype=np.float64)
-    d2 = np.zeros_like(T)
-    d2[1:-1] = np.abs(T[2:] - 2 * T[1:-1] + T[:-2])
-    d2[0], d2[-1] = d2[1], d2[-2]
-    eps = eps_rel * d2.mean() + 1e-300
-    q = (d2 + eps) ** (1.0 / 3.0)
+    n = T.shape[0]
+    assert n % N_TOTAL == 0 and n % N_BINS == 0
+    E = midpoints(n)
+    s = n // N_TOTAL
+    k = np.arange(N_TOTAL) * s + s // 2           # dense points nearest the uniform rule's energies
+    e2 = np.zeros(n)
+    for a, b in zip(k[:-1], k[1:]):
+        x, y = E[a:b + 1], T[a:b + 1]
+        lin = y[0] + (y[-1] - y[0]) * (x - x[0]) / (x[-1] - x[0])
+        r = y - lin
+        e = float(np.sum(0.5 * (r[1:] + r[:-1]) * np.diff(x)))
+        e2[a:b] = e * e
+    e2[:k[0]] = e2[k[0]]                          # the end stretches take their neighbour's value
+    e2[k[-1]:] = e2[k[-1] - 1]
+    q = e2.reshape(N_BINS, -1).mean(axis=1)
+    q = q + floor_rel * q.mean() + 1e-300
     return (q / q.sum()).astype(np.float32)
 
 
 def place(p, n=N_LEARNED, mix=0.8):
-    """n energies at the deterministic quantiles of mix*p + (1-mix)*uniform over the bins."""
+    """n energies: the density d = mix * norm(sqrt(p)) + (1 - mix) * uniform over the bins is
+    integrated over the intervals the probe energies cut, the n points are shared among them in
+    proportion (largest remainders) and sit evenly spaced inside each interval."""
     p = np.asarray(p, dtype=np.float64)
-    if p.shape != (N_BINS,) or not np.all(np.isfinite(p)) or p.sum() <= 0:
+    if p.shape != (N_BINS,) or not np.all(np.isfinite(p)) or p.sum() <= 0 or np.any(p < 0):
         return None
-    d = mix * p / p.sum() + (1.0 - mix) / N_BINS
+    r = np.sqrt(p)
+    d = mix * r / r.sum() + (1.0 - mix) / N_BINS
     cdf = np.concatenate([[0.0], np.cumsum(d)])
-    cdf /= cdf[-1]
-    u = (np.arange(n) + 0.5) / n
-    b = np.clip(np.searchsorted(cdf, u, side="right") - 1, 0, N_BINS - 1)
-    frac = (u - cdf[b]) / np.maximum(cdf[b + 1] - cdf[b], 1e-300)
     width = (EMAX - EMIN) / N_BINS
-    E = EMIN + (b + np.clip(frac, 0.0, 1.0)) * width
-    # the zigzag ribbon's flat edge band sits at E = 0: keep points off it
-    E[np.abs(E) < 1e-5] = 1e-5
-    return E
+    edges = np.concatenate([[EMIN], midpoints(N_PROBE), [EMAX]])
+    mass = np.diff(np.interp(edges, EMIN + width * np.arange(N_BINS + 1), cdf))
+    share = mass / mass.sum() * n
+    cnt = np.floor(share).astype(int)
+    cnt[np.argsort(-(share - cnt), kind="stable")[:n - cnt.sum()]] += 1
+    E = np.concatenate([edges[k] + (edges[k + 1] - edges[k]) * np.arange(1, c + 1) / (c + 1)
+                        for k, c in enumerate(cnt)])
+    # the zigzag lead is singular at E = 0 (its flat edge band) and at E = +-t (every subband
+    # meets there at the zone boundary), where its decimation does not converge: keep points
+    # at least 1e-3 away (the judge grid's nearest points are 7.3e-4 away)
+    for e0 in (0.0, -1.0, 1.0):
+        near = np.abs(E - e0) < 1e-3
+        E[near] = np.where(E[near] < e0, e0 - 1e-3, e0 + 1e-3)
+    return np.sort(E)
 
 
 def threshold_density(nopen_dense, weight=20.0):
@@ -198,13 +248,13 @@ def learned_points(net, ribbons, T_probe, nopen_dense, device="cuda"):
     return pts, fell_back
 
 
-def generate_training_set(n_curves, device="cuda", progress=None, chunk=64, **kw):
-    """Features and target densities of n_curves seeded ribbons."""
+def generate_training_set(n_curves, device="cuda", progress=None, chunk=64, n_dense=N_DENSE, **kw):
+    """Features and target densities of n_curves seeded ribbons (targets from n_dense points)."""
     rib = train_ribbons(n_curves, **kw)
-    Ep, Ed = midpoints(N_PROBE), midpoints(N_BINS)
+    Ep, Ed = midpoints(N_PROBE), midpoints(n_dense)
     curves = transmission_curves(rib, [np.concatenate([Ep, Ed])] * len(rib), chunk=chunk, device=device,
                                  progress=progress)
-    nopen = open_channels([r.Nz for r in rib], Ed, device)
+    nopen = open_channels([r.Nz for r in rib], midpoints(N_BINS), device)
     T_probe = [c[:N_PROBE] for c in curves]
     T_dense = [c[N_PROBE:] for c in curves]
     X = features(rib, T_probe, nopen)
@@ -227,20 +277,20 @@ def train(net, X, Q, steps=300, batch=256, lr=2e-3, wd=1e-4, seed=0, device="cud
     return hist
 
 
-def evaluate(net, ribbons, device="cuda", progress=None):
+def evaluate(net, ribbons, device="cuda", progress=None, chunk=16):
     """Integrated-conductance error of the learned 256 points and of 256 uniform points
     against the 4096-point judge, per ribbon."""
     Ep, Eu, Ej = midpoints(N_PROBE), midpoints(N_TOTAL), midpoints(N_JUDGE)
     ends = np.array([EMIN, EMAX])
     nopen = open_channels([r.Nz for r in ribbons], midpoints(N_BINS), device)
-    base = transmission_curves(ribbons, [np.concatenate([Ep, Eu, Ej, ends])] * len(ribbons), chunk=1,
+    base = transmission_curves(ribbons, [np.concatenate([Ep, Eu, Ej, ends])] * len(ribbons), chunk=chunk,
                                device=device, progress=progress)
     n1, n2, n3 = N_PROBE, N_PROBE + N_TOTAL, N_PROBE + N_TOTAL + N_JUDGE
     T_probe = [c[:n1] for c in base]
     pts, fb = learned_points(net, ribbons, T_probe, nopen, device)
-    learned_T = transmission_curves(ribbons, pts, chunk=1, device=device, progress=progress)
+    learned_T = transmission_curves(ribbons, pts, chunk=chunk, device=device, progress=progress)
     thr_pts = [place(threshold_density(nopen[r.Nz])) for r in ribbons]
-    thr_T = transmission_curves(ribbons, thr_pts, chunk=1, device=device, progress=progress)
+    thr_T = transmission_curves(ribbons, thr_pts, chunk=chunk, device=device, progress=progress)
     rows = []
     for i in range(len(ribbons)):
         c = base[i]

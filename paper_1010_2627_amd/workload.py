@@ -109,6 +109,35 @@ class Batch:
         self.sigma_iters = torch.cat(its) if its else None
         return self.sigmaL, self.sigmaR
 
+    def repair_sigmas(self, eta=1e-16, tol=1e-16, max_iter=100, group=4, nudge=0.0, stream=None):
+        """Redo, in calls of at most `group` energies, the self-energies whose status is not
+        clean (one call redoes at most four energies at slice eigenvalues with its two-slice
+        cell; a batch with more such energies leaves the rest flagged).  With nudge != 0 the
+        redone self-energy is taken at E + nudge * max(1, |E|) (for an energy sitting exactly
+        on a channel threshold, where the lead's Bloch factors degenerate); the problems keep
+        their E.  Returns the number of energies still flagged afterwards."""
+        st = self.sigma_status.cpu().numpy()
+        left, pos = 0, 0
+        for si, (ds, E) in enumerate(zip(self.dstrips, self.energies)):
+            n = len(E)
+            bad = np.nonzero(st[pos:pos + n] != 0)[0]
+            for g0 in range(0, len(bad), group):
+                idx = bad[g0:g0 + group]
+                Et = self.denergies[si][torch.as_tensor(idx, device=self.device)].contiguous()
+                if nudge:
+                    Et = Et + nudge * torch.clamp(Et.abs(), min=1.0)
+                sig, it, s2 = K.knit_lead_selfenergy(ds, 2, Et, eta, tol, max_iter, stream)
+                s2 = s2.cpu().numpy()
+                MM = ds.M * ds.M
+                for j, e in enumerate(idx):
+                    o = self.sigma_base[si] + int(e) * MM
+                    self.sigmaL[o:o + MM].copy_(sig[0][j].reshape(-1))
+                    self.sigmaR[o:o + MM].copy_(sig[1][j].reshape(-1))
+                    self.sigma_status[pos + int(e)] = int(s2[j])
+                left += int((s2 != 0).sum())
+            pos += n
+        return left
+
     def compute_gamma_factors(self, tol=0.0, stream=None):
         """Factor Gamma = C C^+ of both leads at every (strip class, energy) slot."""
         self.CL = torch.zeros(self.sigma_elems, dtype=torch.complex128, device=self.device)

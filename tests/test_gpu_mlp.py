@@ -130,13 +130,12 @@ def _trained(n_curves=1024, steps=1500):
 
 
 @gpu
-def test_sampler_trains_and_its_gain_over_uniform_points_is_measured():
-    """Train on generated curves (own kernels), then place 256 energies on held-out ribbons
-    and measure the integrated-conductance error against the 4096-point grid, next to 256
-    uniform points (the method without the network) and a non-learned threshold-aware
-    placement.  The network must learn (KL to the targets falls) and never fall back;
-    the gain is printed and bounded below by a sanity margin only: on this family even a
-    placement from the test curves' own fine curvature does not beat uniform points."""
+def test_sampler_trains_and_beats_uniform_points():
+    """Train on generated curves (own kernels; targets: where the 256-point trapezoid rule
+    leaves its error), then place 256 energies on 64 held-out ribbons and compare the
+    integrated-conductance error against the 4096-point grid with 256 uniform points (the
+    method without the network).  The network must learn (KL to the targets falls), never
+    fall back, and its mean error must be below the uniform points' mean error."""
     from paper_1010_2627_amd import sampler as S
     net, hist, X, Q = _trained()
     # cross-entropy = H(q) + KL(q || p): only the KL part can be learned
@@ -144,7 +143,7 @@ def test_sampler_trains_and_its_gain_over_uniform_points_is_measured():
     kl0, kl1 = hist[0][1] - H, hist[-1][1] - H
     print(f"\nloss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}, target entropy {H:.4f}, KL {kl0:.4f} -> {kl1:.4f}")
     assert kl1 < 0.7 * kl0, hist
-    test = S.train_ribbons(16, start=100000)       # held out: seeds beyond the training range
+    test = S.train_ribbons(64, start=100000)       # held out: seeds beyond the training range
     rows = S.evaluate(net, test)
     eu = np.array([r["err_uniform"] for r in rows])
     el = np.array([r["err_learned"] for r in rows])
@@ -153,4 +152,4 @@ def test_sampler_trains_and_its_gain_over_uniform_points_is_measured():
           f"(gain {eu.mean() / el.mean():.2f}x, wins {int((el < eu).sum())}/{len(el)}), "
           f"threshold-aware {et.mean():.3e} (gain {eu.mean() / et.mean():.2f}x)")
     assert not any(r["fallback"] for r in rows)
-    assert np.all(np.isfinite(el)) and el.mean() <= 3.0 * eu.mean()
+    assert np.all(np.isfinite(el)) and el.mean() < eu.mean()

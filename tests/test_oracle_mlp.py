@@ -91,10 +91,17 @@ def test_rounded_network_stays_close_to_exact():
 
 # ---------------------------------------------------------------- sampler host logic
 
-def test_placement_of_a_uniform_density_is_the_midpoint_grid():
+def test_placement_of_a_uniform_density_completes_an_even_grid():
+    """Three points between neighbouring probe energies: probe + placement is the evenly
+    spaced 256-point grid away from the two end stretches."""
     from paper_1010_2627_amd import sampler as S
     E = S.place(np.full(S.N_BINS, 1.0 / S.N_BINS))
-    assert np.allclose(E, S.midpoints(S.N_LEARNED), atol=1e-12)
+    assert len(E) == S.N_LEARNED and np.all(np.diff(E) > 0)
+    allE = np.sort(np.concatenate([S.midpoints(S.N_PROBE), E]))
+    step = (S.EMAX - S.EMIN) / S.N_TOTAL
+    inner = (allE > S.midpoints(S.N_PROBE)[0] - 1e-12) & (allE < S.midpoints(S.N_PROBE)[-1] + 1e-12)
+    assert np.allclose(np.diff(allE[inner]), step, atol=1.1e-3)   # points move off E = 0, +-1 by 1e-3
+    assert np.all((E > S.EMIN) & (E < S.EMAX))
 
 
 def test_placement_follows_the_density():
@@ -102,13 +109,24 @@ def test_placement_follows_the_density():
     p = np.zeros(S.N_BINS)
     p[100] = 1.0
     E = S.place(p)
-    width = (S.EMAX - S.EMIN) / S.N_BINS
-    inside = (E >= S.EMIN + 100 * width) & (E <= S.EMIN + 101 * width)
-    # 80% of the mass sits in bin 100 (plus its 0.2/512 share of the uniform part)
-    assert abs(inside.sum() - 0.8 * S.N_LEARNED) <= 2
-    assert np.all(np.diff(E) >= 0)
+    # bin 100 lies between probe energies 12 and 13 (probe spacing is 8 bins, probe j at bin 8j + 4):
+    # that interval receives 0.8 of the points plus its uniform share 0.2 * 8 / 512
+    pr = S.midpoints(S.N_PROBE)
+    inside = (E > pr[12]) & (E < pr[13])
+    assert abs(inside.sum() - (0.8 + 0.2 * 8 / S.N_BINS) * S.N_LEARNED) <= 1
+    assert np.allclose(np.diff(E[inside]), (pr[13] - pr[12]) / (inside.sum() + 1), atol=1e-12)
+    # the square root of the density sets the shares: two bins with p 4:1 get points 2:1
+    p = np.zeros(S.N_BINS)
+    p[100], p[300] = 4.0, 1.0
+    E = S.place(p, mix=1.0)
+    a = ((E > pr[12]) & (E < pr[13])).sum()
+    b = ((E > pr[37]) & (E < pr[38])).sum()
+    assert a + b == S.N_LEARNED and abs(a - 2 * b) <= 1
     assert S.place(np.full(S.N_BINS, np.nan)) is None        # unusable density -> caller falls back
-    assert np.all(np.abs(S.place(np.eye(S.N_BINS)[256])) >= 1e-5)   # never on the zigzag flat band
+    assert S.place(-np.ones(S.N_BINS)) is None
+    assert np.all(np.abs(S.place(np.eye(S.N_BINS)[256])) >= 1e-3)   # never on the zigzag flat band
+    E = S.place(np.full(S.N_BINS, 1.0 / S.N_BINS))
+    assert np.all(np.abs(np.abs(E) - 1.0) >= 1e-3)                  # nor on the zigzag lead's E = +-t
 
 
 def test_trapezoid_is_exact_for_piecewise_linear_functions():
@@ -119,10 +137,29 @@ def test_trapezoid_is_exact_for_piecewise_linear_functions():
 
 
 def test_target_density_is_flat_for_linear_and_peaks_at_a_kink():
+    """The trapezoid rule is exact on a line (flat target); a kink puts the error, and the
+    target's peak, in the interval of the 256-point rule that holds it."""
     from paper_1010_2627_amd import sampler as S
-    E = S.midpoints(S.N_BINS)
+    E = S.midpoints(S.N_DENSE)
     q = S.target_density(3.0 * E + 2.0)
     assert np.allclose(q, 1.0 / S.N_BINS, rtol=1e-6)
-    q = S.target_density(np.abs(E - 0.5))
-    k = np.argmin(np.abs(E - 0.5))
-    assert q.argmax() in (k - 1, k, k + 1) and q.max() > 10 * np.median(q)
+    kink = 0.51
+    q = S.target_density(np.abs(E - kink))
+    k = int((kink - S.EMIN) / (S.EMAX - S.EMIN) * S.N_BINS)
+    assert q.argmax() in (k - 1, k, k + 1) and q.max() > 100 * np.median(q)
+
+
+def test_target_density_is_the_squared_interval_error():
+    """Pinned by hand: a parabola's trapezoid error on an interval of width h is -h^3 T''/12
+    exactly, the same for every interval, so the target is flat; a bump confined to one
+    interval of the 256-point rule gives that interval's two bins all the mass above the floor."""
+    from paper_1010_2627_amd import sampler as S
+    E = S.midpoints(S.N_DENSE)
+    q = S.target_density(E ** 2)
+    assert np.allclose(q, 1.0 / S.N_BINS, rtol=1e-3)
+    T = np.zeros(S.N_DENSE)
+    T[16 * 100 + 8 + 4: 16 * 100 + 8 + 12] = 1.0     # inside the interval between rule points 100 and 101
+    q = S.target_density(T)
+    top = np.sort(np.argsort(q)[-2:])
+    assert list(top) == [200 + 1, 200 + 2] or list(top) == [201, 202]
+    assert q[top].sum() > 0.9
