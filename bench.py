@@ -298,6 +298,8 @@ def main():
                          "(for profiler runs)")
     ap.add_argument("--autotune", action="store_true",
                     help="time the sweep's launch shapes on a sample of the batch first and use the best")
+    ap.add_argument("--graph-only", action="store_true",
+                    help="time only the knitting of a system of any shape (its JSON object alone)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device copy of this size (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -313,6 +315,9 @@ def main():
 
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.graph_only:
+        print(json.dumps(graph_leg()))
+        return
     if cfg["kind"] == "sampler":
         sampler_bench(args, cfg)
         return
