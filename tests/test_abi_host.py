@@ -285,6 +285,58 @@ def test_projected_path_argument_checks(K):
     assert tp(s, 1, _probs([(0, 0, 0.1, 0, 0, 0, 0)]).ctypes.data, FAKE, 1, FAKE, FAKE, FAKE, None) == K.KNIT_E_ARG
 
 
+def test_observable_entry_points_argument_checks(K):
+    """Transmission eigenvalues, local observables and the conductance matrix reject bad
+    arguments before any device call (fake device pointers are never dereferenced)."""
+    lib = K._lib
+    s = (K.KnitStrip * 1)(_strip(M=16))
+    probs = _probs([(0, 8, 0.1, 0, 0, 0, 0), (0, 8, 0.2, 0, 0, 256, 128)])
+    ph = probs.ctypes.data
+    # transmission eigenvalues
+    te = lambda **kw: lib.knit_transmission_eigenvalues(
+        s, 1, ph, FAKE, 2, kw.get("CR", FAKE), kw.get("G1Np", FAKE), kw.get("ld", 16), kw.get("tn", FAKE), None,
+        None, None, kw.get("ws", FAKE), kw.get("wsb", 1 << 40), None)
+    assert te(CR=None) == K.KNIT_E_ARG
+    assert te(G1Np=None) == K.KNIT_E_ARG
+    assert te(tn=None) == K.KNIT_E_ARG
+    assert te(ld=15) == K.KNIT_E_ARG                    # ld below the largest M
+    assert te(ws=None) == K.KNIT_E_WORKSPACE
+    need = lib.knit_transmission_eigenvalues_workspace(s, 1, ph, 2)
+    assert need > 0 and te(wsb=need - 1) == K.KNIT_E_WORKSPACE
+    assert lib.knit_transmission_eigenvalues(s, 1, None, None, 0, None, None, 16, None, None, None, None, None, 0,
+                                             None) == K.KNIT_OK
+    # local observables
+    lo = lambda **kw: lib.knit_local_observables(
+        s, 1, ph, FAKE, 2, FAKE, FAKE, FAKE, kw.get("CL", FAKE), 0, kw.get("blk", FAKE), FAKE, FAKE, FAKE, FAKE,
+        kw.get("ws", FAKE), kw.get("wsb", 1 << 40), None)
+    assert lo(CL=None) == K.KNIT_E_ARG
+    assert lo(blk=None) == K.KNIT_E_ARG
+    assert lo(ws=None) == K.KNIT_E_WORKSPACE
+    need = lib.knit_local_observables_workspace(s, 1, ph, 2, 0)
+    assert need > 0 and lo(wsb=need - 1) == K.KNIT_E_WORKSPACE
+    wide = (K.KnitStrip * 1)(_strip(M=544))
+    assert lib.knit_local_observables(wide, 1, ph, FAKE, 2, FAKE, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, FAKE, FAKE,
+                                      FAKE, 1 << 40, None) == K.KNIT_E_UNSUPPORTED
+    # conductance matrix: side leads on valid slices only, at most KNIT_MAX_SIDE_LEADS
+    from paper_1010_2627_amd.knit import LEAD_DTYPE
+    side = np.zeros(2, dtype=LEAD_DTYPE)
+    side["slice"] = [3, 5]
+    cm = lambda **kw: lib.knit_conductance_matrix(
+        s, 1, ph, FAKE, 2, FAKE, FAKE, FAKE, FAKE, FAKE, kw.get("n_side", 1), kw.get("side", side.ctypes.data),
+        kw.get("side_dev", FAKE), FAKE, FAKE, 0, kw.get("T", FAKE), FAKE, kw.get("ws", FAKE),
+        kw.get("wsb", 1 << 40), None)
+    assert cm(n_side=-1) == K.KNIT_E_ARG
+    assert cm(n_side=7) == K.KNIT_E_ARG
+    assert cm(side_dev=None) == K.KNIT_E_ARG
+    assert cm(T=None) == K.KNIT_E_ARG
+    bad = side.copy()
+    bad["slice"] = [3, 8]                               # slice 8 is past L = 8
+    assert cm(side=bad.ctypes.data) == K.KNIT_E_ARG
+    assert cm(ws=None) == K.KNIT_E_WORKSPACE
+    need = lib.knit_conductance_matrix_workspace(s, 1, ph, 2, 1, 0)
+    assert need > 0 and cm(wsb=need - 1) == K.KNIT_E_WORKSPACE
+
+
 # ---------------------------------------------------------------- knitting of systems of any shape
 
 def test_library_exports_every_graph_entry(K):
