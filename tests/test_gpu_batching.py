@@ -203,3 +203,57 @@ def test_graph_capture_of_a_refined_whole_propagator_step_replays_bitwise():
         T_g = b.transmission(G1N_g)[0]
     torch.cuda.synchronize()
     _replay_equals(g, [T_g, st_g], [T_eager, st_eager])
+
+
+@gpu
+def test_uneven_workload_stated_form_sampled_against_oracle():
+    """Strips of the uneven workload itself (the 512-strip layout and its seeds; the ones with
+    W <= 64 and L <= 700, so the oracle is quick) at two of its 32 energies, in the workload's
+    stated form: FP32 elimination with FP64 refinement on the projected path, the whole step
+    captured in one graph and replayed.  Every problem is within 1e-6 per open channel of the
+    oracle, which uses its own Bloch-mode self-energies."""
+    from oracle import leads as OL, rgf as OR
+    from paper_1010_2627_amd import inputs, workload
+    lay = inputs.uneven_layout(512)
+    pick = [i for i in range(512) if lay.widths[i] <= 64 and lay.lengths[i] <= 700][:6]
+    assert len(pick) == 6
+    widths = sorted(set(int(lay.widths[i]) for i in pick))
+    cls = {W: k for k, W in enumerate(widths)}
+    strips = [inputs.square_strip(W) for W in widths]
+    reals = [workload.Realization(cls[int(lay.widths[i])],
+                                  inputs.onsite_disorder(strips[cls[int(lay.widths[i])]], int(lay.lengths[i]),
+                                                         float(lay.ws[i]), int(lay.seeds[i])), f"strip{i}")
+             for i in pick]
+    E = inputs.midpoint_grid(-3.9, 3.9, 32)[[5, 20]]
+    b = workload.Batch(strips, reals, [E for _ in strips])
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):                   # eager first: the workspaces exist before capture
+        b.compute_sigmas()
+        b.compute_gamma_factors()
+        G, _, st = b.sweep_projected(precision="fp32_refine")
+        b.transmission_projected(G)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        b.compute_sigmas()
+        b.compute_gamma_factors()
+        G_g, _, st_g = b.sweep_projected(precision="fp32_refine")
+        T_g = b.transmission_projected(G_g)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    T = T_g.cpu().numpy()
+    st = st_g.cpu().numpy()
+    assert int(((st & ~8) != 0).sum()) == 0
+    for ri, r in enumerate(b.realizations):
+        s = b.strips[r.strip]
+        V = s.V_dense()
+        sL = np.stack([OL.sigma_modes(s.H0, V, e, "L") for e in E])
+        sR = np.stack([OL.sigma_modes(s.H0, V, e, "R") for e in E])
+        Tref = OR.transmission_lr(sL, sR, OR.rgf_forward(s.H0, V, r.onsite, E, sL, sR)["G1N"])
+        nopen = OL.n_open_square(s.M, E)
+        for ei in range(len(E)):
+            p = ri * len(E) + ei
+            assert abs(T[p] - Tref[ei]) <= 1e-6 * max(1, nopen[ei]), (pick[ri], E[ei], T[p], Tref[ei])
