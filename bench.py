@@ -305,18 +305,23 @@ def stated_form(b, knit, G1Np, ws_for, T64, wall64, nopen, steps, autotuned):
         T_e, st_e = body()
         T_e, st_e = T_e.clone(), st_e.clone()
     torch.cuda.synchronize()
+    progress("stated form: eager refined step done")
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s2):
         T_g, st_g = body()
     torch.cuda.synchronize()
+    progress("stated form: step captured")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(s2):
-        e0.record(s2)
-        for _ in range(steps):
+    ts = []
+    for _ in range(steps):
+        with torch.cuda.stream(s2):
+            e0.record(s2)
             g.replay()
-        e1.record(s2)
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 1e3 / steps
+            e1.record(s2)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+        progress(f"stated form: replay {len(ts)}/{steps}: {ts[-1]:.2f} s")
+    t = float(np.mean(ts))
     Tg, Te, st = T_g.cpu().numpy(), T_e.cpu().numpy(), st_g.cpu().numpy()
     d = np.abs(Tg - T64) / np.maximum(1, nopen)
     return {"precision": prec, "graph_captured": True, "autotuned": bool(autotuned),
