@@ -129,8 +129,9 @@ size_t knit_graph_workspace(const knit_graph_plan *plan, int32_t P);
  *             gll_off, leads in order, each lead's sites in its own order
  *   pstatus   device [P] status bits (KNIT_P_SINGULAR: a zero pivot;
  *             KNIT_P_NONFINITE: a non-finite result; outputs NaN then)
- * The plan's host memory is read by an asynchronous copy into the
- * workspace: destroy the plan only after the stream's work is done.
+ * P = 0 returns KNIT_OK and enqueues nothing.  The plan's host memory is
+ * read by an asynchronous copy into the workspace: destroy the plan only
+ * after the stream's work is done.
  */
 int knit_graph_transmission(const knit_graph_plan *plan, const knit_graph_problem *probs, int32_t P,
                             const knit_z *hop, const knit_z *onsite, const knit_z *sigma, double *T, knit_z *GLL,

@@ -966,7 +966,9 @@ extern "C" size_t knit_graph_workspace(const knit_graph_plan *plan, int32_t P) {
 extern "C" int knit_graph_transmission(const knit_graph_plan *plan, const knit_graph_problem *probs, int32_t P,
                                        const knit_z *hop, const knit_z *onsite, const knit_z *sigma, double *T,
                                        knit_z *GLL, int32_t *pstatus, void *ws, size_t ws_bytes, void *stream) {
-  if (!plan || P < 1 || !probs || !onsite || !sigma || !T || !pstatus) return KNIT_E_ARG;
+  if (!plan || P < 0) return KNIT_E_ARG;
+  if (P == 0) return KNIT_OK;
+  if (!probs || !onsite || !sigma || !T || !pstatus) return KNIT_E_ARG;
   if (plan->info.nnz > 0 && !hop) return KNIT_E_ARG;
   const size_t need = knit_graph_workspace(plan, P);
   if (!ws || ws_bytes < need) return KNIT_E_WORKSPACE;

@@ -449,8 +449,10 @@ def test_graph_transmission_validates_before_any_device_call(K):
     L = GR._lib
     assert L.knit_graph_transmission(None, FAKE, 1, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 1 << 40,
                                      None) == K.KNIT_E_ARG
-    assert L.knit_graph_transmission(p.handle, FAKE, 0, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 1 << 40,
+    assert L.knit_graph_transmission(p.handle, FAKE, -1, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 1 << 40,
                                      None) == K.KNIT_E_ARG
+    assert L.knit_graph_transmission(p.handle, None, 0, None, None, None, None, None, None, None, 0,
+                                     None) == K.KNIT_OK          # empty batch: nothing to do
     assert L.knit_graph_transmission(p.handle, FAKE, 1, None, FAKE, FAKE, FAKE, None, FAKE, FAKE, 1 << 40,
                                      None) == K.KNIT_E_ARG
     assert L.knit_graph_transmission(p.handle, FAKE, 1, FAKE, FAKE, FAKE, FAKE, None, FAKE, None, 1 << 40,

@@ -267,3 +267,38 @@ def test_strip_agrees_with_slice_sweep():
     G1N, _, _, status = b.sweep("fp64", gnn=False)
     Ts = b.transmission(G1N)[0].cpu().numpy()
     assert np.abs(Ts - T[:, 1, 0]).max() < 1e-10, (Ts, T[:, 1, 0])
+
+
+@gpu
+def test_single_lead_and_lead_covering_everything():
+    """Degenerate plans: one lead (T_00 only), and a lead holding every site (no knitting
+    step: G is lead 0's block inverse alone)."""
+    Lx, Ly = 7, 5
+    g = inputs.square_lattice_graph(inputs.rectangle_with_hole(Lx, Ly), flux=0.13)
+    left = _sides(g, Lx, Ly, ["left"])
+    ons = inputs.graph_disorder(g, 1.4, seed=12)
+    _check(g, left, [-1.2, 0.9], ons, _synthetic(left, 1, 2, 900))
+    every = [list(range(g.N))]
+    sig = [inputs.synthetic_sigma(g.N, 2, seed=901, rank=8)]
+    _check(g, every, [-0.4, 1.6], ons, sig)
+
+
+@gpu
+def test_mode_boundaries_and_a_detached_cluster():
+    """Interface dimensions 64 and 65 (the two register modes' edge) and 128 / 129 (register
+    and slab mode), plus a small cluster attached to no lead (a closed part: it must not
+    disturb T)."""
+    from paper_1010_2627_amd import graph as GR
+    for W, Lx, want in ((31, 9, 0), (32, 6, 1), (63, 4, 1), (64, 4, 2)):
+        g = inputs.square_lattice_graph(inputs.rectangle_with_hole(Lx, W))
+        leads = _sides(g, Lx, W, ["left", "right"])
+        D = GR.plan_create(g.N, 1, g.row_ptr, g.col, leads).info()["dim"]
+        mode = 0 if D <= 64 else (1 if D <= 128 else 2)
+        assert mode == want, (W, D)
+        _check(g, leads, [0.37], inputs.graph_disorder(g, 1.0, seed=W), _synthetic(leads, 1, 1, 1000 + W),
+               want_mode=want)
+    # detached 2 x 2 cluster beside a 6 x 4 sample
+    sites = inputs.rectangle_with_hole(6, 4) + [(20, 0), (21, 0), (20, 1), (21, 1)]
+    g = inputs.square_lattice_graph(sites)
+    leads = _sides(g, 6, 4, ["left", "right"])
+    _check(g, leads, [-0.83, 1.21], inputs.graph_disorder(g, 2.0, seed=77), _synthetic(leads, 1, 2, 1100))
