@@ -240,6 +240,32 @@ int knit_set_refine_threshold(double threshold);
 double knit_get_refine_threshold(void);
 
 /*
+ * How knit_lead_selfenergy forms its double-double matrix products (section
+ * 5.3-B: the leads' self-energies by decimation).
+ *   KNIT_PRODUCTS_VECTOR  (default) double-double arithmetic on the vector
+ *                         units;
+ *   KNIT_PRODUCTS_INT8    both factors split into signed 7-bit
+ *                         digits (rows of the left factor and columns of the
+ *                         right one scaled by powers of two; 16 digits for a
+ *                         double-double factor, 8 for an FP64 one), digit
+ *                         planes multiplied exactly on the INT8 matrix cores
+ *                         with int32 sums, digit pairs of combined weight below
+ *                         2^-124 of the scales dropped, the rest summed in
+ *                         double-double: a normwise relative error of about
+ *                         2^-106 per product, as double-double's own.  The
+ *                         retry pass (energies at slice eigenvalues) always
+ *                         uses the vector products.  Where the decimated
+ *                         couplings mix parts of very different size the
+ *                         row- and column-relative accuracy can stall the
+ *                         doubling (KNIT_P_NOCONV / KNIT_P_NONFINITE).
+ * Process-wide; returns KNIT_E_ARG for any other value.
+ */
+#define KNIT_PRODUCTS_VECTOR 0
+#define KNIT_PRODUCTS_INT8 1
+int knit_set_selfenergy_products(int32_t mode);
+int32_t knit_get_selfenergy_products(void);
+
+/*
  * Left-to-right slice recursion (section 1, basic RGF) for a batch of P
  * problems, in one persistent launch.  Per problem:
  *   g_1 = (E - H_1 - Sigma_L - [L = 1] Sigma_R)^{-1}

@@ -191,6 +191,16 @@ int knit_set_refine_threshold(double threshold) {
 
 double knit_get_refine_threshold(void) { return sweep_get_refine_threshold(); }
 
+int knit_set_selfenergy_products(int32_t mode) {
+  if (mode != KNIT_PRODUCTS_VECTOR && mode != KNIT_PRODUCTS_INT8) return KNIT_E_ARG;
+  decimation_products_set(mode == KNIT_PRODUCTS_INT8);
+  return KNIT_OK;
+}
+
+int32_t knit_get_selfenergy_products(void) {
+  return decimation_products_get() ? KNIT_PRODUCTS_INT8 : KNIT_PRODUCTS_VECTOR;
+}
+
 int knit_sweep_tuning_set(int32_t precision, int32_t cls, const knit_sweep_tuning *t) {
   if (!precision_ok(precision) || cls < 0 || cls >= KNIT_TUNING_CLASSES) return KNIT_E_ARG;
   if (t && !sweep_tuning_valid(32 * (cls + 1), *t)) return KNIT_E_ARG;

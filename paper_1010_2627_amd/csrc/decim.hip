@@ -58,6 +58,8 @@
 // per call are redone, when 2M fits the matrix-core inverse; any other failing
 // energy gets KNIT_P_NOCONV and NaN output.
 
+#include <atomic>
+
 #include "knit_internal.h"
 #include "knit_mfma.h"
 
@@ -101,6 +103,8 @@ struct Slab {
   size_t bytes;
   size_t z[17];               // double-double [M][M] buffers
   size_t x64, scr, xi64;      // FP64: padded [Mp][Mp], elimination scratch, natural [M][M]
+  size_t oz_a, oz_b;          // digit planes of the two factors of a product (INT8 matrix cores)
+  size_t oz_ea, oz_eb;        // their row / column exponents (int32 [M])
 };
 enum { ZEPS_S, ZEPS_R, ZEPS, ZA, ZXA, ZXB, ZR, ZGA, ZGB, ZT1, ZT2, ZA0, ZA1, ZB0, ZB1, ZVF, ZVB };
 
@@ -119,6 +123,15 @@ Slab slab_of(int M) {
   off += ((inverse_fp64_scratch_elems(M) * sizeof(D)) + 255) & ~size_t(255);
   s.xi64 = off;
   off += (((size_t)M * M * sizeof(D)) + 255) & ~size_t(255);
+  const size_t planes = ((2 * 16 * (size_t)((M + 31) / 32 * 32) * ((M + 63) / 64 * 64)) + 255) & ~size_t(255);
+  s.oz_a = off;
+  off += planes;
+  s.oz_b = off;
+  off += planes;
+  s.oz_ea = off;
+  off += (((size_t)M * sizeof(int32_t)) + 255) & ~size_t(255);
+  s.oz_eb = off;
+  off += (((size_t)M * sizeof(int32_t)) + 255) & ~size_t(255);
   s.bytes = off;
   return s;
 }
@@ -543,6 +556,218 @@ __global__ void dec_status_kernel(const DecState *st, int nE, int max_iter, int3
   if (iters) iters[e] = st[e].iters < max_iter ? st[e].iters : max_iter;
 }
 
+// ---------------------------------------------------------------- products on the INT8 matrix cores
+//
+// A double-double (or FP64) complex product C = A B taken exactly enough for
+// double-double by splitting both operands into signed 7-bit digits and
+// multiplying the digit planes on the INT8 matrix cores
+// (v_mfma_i32_16x16x64_i8, exact int32 sums), the splitting scheme of Ozaki
+// and co-workers with integer slices:
+//   * every row r of A (every column c of B) is scaled by a power of two 2^-e
+//     so that its largest |re|, |im| is below 1;
+//   * a scaled value v is written as sum_i d_i 2^-(6 + 7 i), i < S, with
+//     balanced digits |d_i| <= 64 (d_i = rint of the remainder times
+//     2^(6 + 7 i); each remainder is exact in double-double);
+//   * digit planes multiply exactly: |sum_k a_i b_j| <= 64^2 K, and the sums
+//     of one weight 2^-(12 + 7 d), d = i + j, stay below 2^31 for K <= 1024;
+//   * pairs with i + j >= S are dropped (their weight is below 2^-(12 + 7 S)
+//     of the row and column scales), so S = 16 digits carry 112 bits, enough
+//     for a double-double result (15 digits measured 1e-31 of the scales on
+//     random operands, too close to double-double's 2^-106 for the 60
+//     doubling steps);
+//   * Re C = sum_d (P_d - Q_d) 2^-(12+7d), Im C = sum_d R_d 2^-(12+7d) with
+//     P = ar br, Q = ai bi, R = ar bi + ai br, summed in double-double from
+//     the smallest weight, times 2^(e_r + e_c).
+// Planes are stored zero-padded to [Mr][Mk] (rows to 32, k to 64): A as
+// [2S][Mr][Mk] (digit i of re at plane 2i, of im at 2i + 1), B transposed,
+// [2S][Mc][Mk] with the column index first.
+
+constexpr int OZ_S = 16;        // digits of a double-double operand
+constexpr int OZ_S64 = 8;       // digits of an FP64 operand (56 bits)
+constexpr int OZ_BAD = -100000; // exponent of a line holding a non-finite value
+
+typedef int oz_v4i __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int oz_rows(int M) { return (M + 31) / 32 * 32; }
+__host__ __device__ inline int oz_kpad(int M) { return (M + 63) / 64 * 64; }
+__host__ __device__ inline size_t oz_plane_bytes(int M) { return (size_t)oz_rows(M) * oz_kpad(M); }
+
+__device__ __forceinline__ double oz_hi(dd v) { return v.hi; }
+__device__ __forceinline__ double oz_hi(double v) { return v; }
+__device__ __forceinline__ dd oz_dd(dd v) { return v; }
+__device__ __forceinline__ dd oz_dd(double v) { return dd{v, 0.0}; }
+
+// Exponent of every row (COLS = false) or column (COLS = true) of X [M][M]
+// (complex, element type T = cpx<dd> or cpx<double>), per energy: the
+// smallest e with max |re|, |im| of the line below 2^e.  Rows: one wave per
+// row, lanes along the row; columns: 64 columns per workgroup, four row
+// groups reduced in LDS.  Reads are coalesced either way.
+template <class T, bool COLS>
+__global__ void __launch_bounds__(256) oz_exp_kernel(const T *X, int64_t stride_bytes, int M, int32_t *exps,
+                                                     int64_t exp_stride, const DecState *st, int check) {
+  __shared__ double sm[4][64];
+  __shared__ int sf[4][64];
+  const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
+  const T *Xe = reinterpret_cast<const T *>(reinterpret_cast<const char *>(X) + (int64_t)e * stride_bytes);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double m = 0.0;
+  int fin = 1;
+  int line;
+  if (!COLS) {
+    line = blockIdx.x * 4 + wv;
+    if (line < M)
+      for (int t = lane; t < M; t += 64) {
+        const T v = Xe[(int64_t)line * M + t];
+        m = fmax(m, fmax(fabs(oz_hi(v.re)), fabs(oz_hi(v.im))));
+        fin &= isfinite(oz_hi(v.re)) && isfinite(oz_hi(v.im));
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      m = fmax(m, __shfl_xor(m, off, 64));
+      fin &= __shfl_xor(fin, off, 64);
+    }
+    if (lane == 0 && line < M) exps[(int64_t)e * exp_stride + line] = !fin ? OZ_BAD : (m > 0.0 ? ilogb(m) + 1 : 0);
+  } else {
+    line = blockIdx.x * 64 + lane;
+    if (line < M)
+      for (int t = wv; t < M; t += 4) {
+        const T v = Xe[(int64_t)t * M + line];
+        m = fmax(m, fmax(fabs(oz_hi(v.re)), fabs(oz_hi(v.im))));
+        fin &= isfinite(oz_hi(v.re)) && isfinite(oz_hi(v.im));
+      }
+    sm[wv][lane] = m;
+    sf[wv][lane] = fin;
+    __syncthreads();
+    if (wv == 0 && line < M) {
+      for (int g = 1; g < 4; ++g) {
+        m = fmax(m, sm[g][lane]);
+        fin &= sf[g][lane];
+      }
+      exps[(int64_t)e * exp_stride + line] = !fin ? OZ_BAD : (m > 0.0 ? ilogb(m) + 1 : 0);
+    }
+  }
+}
+
+// Digit planes of X (rows scaled, or transposed with columns scaled), S digits.
+template <class T, bool COLS>
+__global__ void __launch_bounds__(EW) oz_digit_kernel(const T *X, int64_t stride_bytes, int M, int S,
+                                                      const int32_t *exps, int64_t exp_stride, int8_t *planes,
+                                                      int64_t plane_stride, const DecState *st, int check) {
+  const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
+  const T *Xe = reinterpret_cast<const T *>(reinterpret_cast<const char *>(X) + (int64_t)e * stride_bytes);
+  const int Mr = oz_rows(M), Mk = oz_kpad(M);
+  const int64_t pb = (int64_t)Mr * Mk;
+  int8_t *Pe = planes + (int64_t)e * plane_stride;
+  for (int64_t idx = blockIdx.x * (int64_t)EW + threadIdx.x; idx < pb; idx += (int64_t)gridDim.x * EW) {
+    const int line = (int)(idx / Mk), k = (int)(idx % Mk);   // line: row of A, or column of B
+    dd vr{0.0, 0.0}, vi{0.0, 0.0};
+    if (line < M && k < M) {
+      const T v = COLS ? Xe[(int64_t)k * M + line] : Xe[(int64_t)line * M + k];
+      const int ex = exps[(int64_t)e * exp_stride + line];
+      const int sc = ex == OZ_BAD ? 0 : -ex;
+      const dd r = oz_dd(v.re), im = oz_dd(v.im);
+      vr = dd{ldexp(r.hi, sc), ldexp(r.lo, sc)};
+      vi = dd{ldexp(im.hi, sc), ldexp(im.lo, sc)};
+      if (ex == OZ_BAD) vr = vi = dd{0.0, 0.0};
+    }
+    for (int i = 0; i < S; ++i) {
+      const double w = ldexp(1.0, 6 + 7 * i);
+      const double dr = rint(vr.hi * w), di = rint(vi.hi * w);
+      vr = two_sum((vr.hi * w - dr) / w, vr.lo);   // exact: x - rint(x), power-of-two scaling
+      vi = two_sum((vi.hi * w - di) / w, vi.lo);
+      Pe[(2 * i) * pb + idx] = (int8_t)(int)dr;
+      Pe[(2 * i + 1) * pb + idx] = (int8_t)(int)di;
+    }
+  }
+}
+
+// C_e = cI I + (+/-) A_e B_e from the digit planes (SA digits of A, SB of B,
+// pairs with i + j < OZ_S).  Workgroup: a 32 x 32 tile of C, four waves of
+// 16 x 16; the B digits of a k-block sit in registers, the A digits come from
+// LDS one digit at a time.
+template <int SA, int SB>
+__global__ void __launch_bounds__(256) oz_gemm_kernel(const int8_t *Ap, const int32_t *ea, const int8_t *Bp,
+                                                      const int32_t *eb, int64_t plane_stride, int64_t exp_stride,
+                                                      Z *C, int64_t c_stride_bytes, int M, double cI, int negate,
+                                                      const DecState *st, int check) {
+  __shared__ __attribute__((aligned(16))) int8_t As[2 * SA][32][64];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2 * SB][32][64];
+  const int e = blockIdx.y;
+  if (dec_skip(st, e, check)) return;
+  const int Mr = oz_rows(M), Mk = oz_kpad(M);
+  const int64_t pb = (int64_t)Mr * Mk;
+  const int tiles_n = Mr / 32;
+  const int tile = blockIdx.x;
+  const int r0 = (tile / tiles_n) * 32, c0 = (tile % tiles_n) * 32;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int8_t *Ae = Ap + (int64_t)e * plane_stride, *Be = Bp + (int64_t)e * plane_stride;
+  oz_v4i P[OZ_S], Q[OZ_S], R[OZ_S];
+#pragma unroll
+  for (int d = 0; d < OZ_S; ++d) P[d] = Q[d] = R[d] = oz_v4i{0, 0, 0, 0};
+  for (int k0 = 0; k0 < Mk; k0 += 64) {
+    // stage the k-block: 16 bytes per load, rows of 64 bytes
+    for (int q = tid; q < 2 * SA * 32 * 4; q += 256) {
+      const int p = q / 128, rr = (q / 4) % 32, part = q % 4;
+      *reinterpret_cast<oz_v4i *>(&As[p][rr][16 * part]) =
+          *reinterpret_cast<const oz_v4i *>(Ae + p * pb + (int64_t)(r0 + rr) * Mk + k0 + 16 * part);
+    }
+    for (int q = tid; q < 2 * SB * 32 * 4; q += 256) {
+      const int p = q / 128, cc = (q / 4) % 32, part = q % 4;
+      *reinterpret_cast<oz_v4i *>(&Bs[p][cc][16 * part]) =
+          *reinterpret_cast<const oz_v4i *>(Be + p * pb + (int64_t)(c0 + cc) * Mk + k0 + 16 * part);
+    }
+    __syncthreads();
+    oz_v4i br[SB], bi[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      br[j] = *reinterpret_cast<const oz_v4i *>(&Bs[2 * j][16 * wc + (l & 15)][16 * (l >> 4)]);
+      bi[j] = *reinterpret_cast<const oz_v4i *>(&Bs[2 * j + 1][16 * wc + (l & 15)][16 * (l >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < SA; ++i) {
+      const oz_v4i ar = *reinterpret_cast<const oz_v4i *>(&As[2 * i][16 * wr + (l & 15)][16 * (l >> 4)]);
+      const oz_v4i ai = *reinterpret_cast<const oz_v4i *>(&As[2 * i + 1][16 * wr + (l & 15)][16 * (l >> 4)]);
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        if (i + j >= OZ_S) continue;
+        P[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, br[j], P[i + j], 0, 0, 0);
+        Q[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi[j], Q[i + j], 0, 0, 0);
+        R[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, bi[j], R[i + j], 0, 0, 0);
+        R[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, br[j], R[i + j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane l holds rows 4 (l / 16) + q, column l % 16 of the wave's tile
+  Z *Ce = reinterpret_cast<Z *>(reinterpret_cast<char *>(C) + (int64_t)e * c_stride_bytes);
+  const int c = c0 + 16 * wc + (l & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + 16 * wr + 4 * (l >> 4) + q;
+    dd re{0.0, 0.0}, im{0.0, 0.0};
+#pragma unroll
+    for (int d = OZ_S - 1; d >= 0; --d) {
+      const double wgt = ldexp(1.0, -12 - 7 * d);
+      re = r_add(re, dd{(double)((long long)P[d][q] - (long long)Q[d][q]) * wgt, 0.0});
+      im = r_add(im, dd{(double)R[d][q] * wgt, 0.0});
+    }
+    if (r >= M || c >= M) continue;
+    const int er = ea[(int64_t)e * exp_stride + r], ec = eb[(int64_t)e * exp_stride + c];
+    Z v;
+    if (er == OZ_BAD || ec == OZ_BAD) {
+      const double qn = __builtin_nan("");
+      v = Z{dd{qn, 0.0}, dd{qn, 0.0}};
+    } else {
+      const int sc = er + ec;
+      v = Z{dd{ldexp(re.hi, sc), ldexp(re.lo, sc)}, dd{ldexp(im.hi, sc), ldexp(im.lo, sc)}};
+    }
+    if (negate) v = c_neg(v);
+    if (cI != 0.0 && r == c) v.re = r_add(v.re, dd{cI, 0.0});
+    Ce[(int64_t)r * M + c] = v;
+  }
+}
+
 #pragma clang fp contract(fast)
 
 // Host-side launch helpers.
@@ -555,6 +780,7 @@ struct Ctx {
   const int *emap;     // slot -> energy (retry pass), or NULL
   int gx_cap;          // GEMM grid x cap (tiles are strided over it), 0 = one block per tile
   hipStream_t stream;
+  int oz;              // double-double products on the INT8 matrix cores (else the vector units)
   Z *zb(int i) const { return reinterpret_cast<Z *>(ws + sl.z[i]); }
   int gx(int m) const {
     const int tiles = ((m + GT - 1) / GT) * ((m + GT - 1) / GT);
@@ -562,7 +788,46 @@ struct Ctx {
   }
 };
 
+// Double-double products on the INT8 matrix cores (digit planes) when enabled,
+// else on the vector units (process-wide; knit_set_selfenergy_products).
+// Off by default: on the slice dimension 512 spinful lead the doubling
+// diverged at 2 of 64 energies with the digit-plane products (their
+// accuracy is relative to each row's and column's largest entry), and the
+// step was only 1.18x faster.
+std::atomic<int> g_int8_products{0};
+
+// C = cI I +/- A B with A [M][M] double-double (buffer a) and B double-double
+// (buffer b) or FP64 (the inverse X0, b < 0), on the INT8 matrix cores.
+template <class TB>
+hipError_t gemm_oz(const Ctx &c, int a, const TB *Bsrc, int out, double cI, int neg, int check) {
+  const int M = c.M, Mr = oz_rows(M);
+  const int64_t st = (int64_t)c.sl.bytes;
+  int8_t *Ap = reinterpret_cast<int8_t *>(c.ws + c.sl.oz_a), *Bp = reinterpret_cast<int8_t *>(c.ws + c.sl.oz_b);
+  int32_t *ea = reinterpret_cast<int32_t *>(c.ws + c.sl.oz_ea), *eb = reinterpret_cast<int32_t *>(c.ws + c.sl.oz_eb);
+  const int64_t es = st / (int64_t)sizeof(int32_t);
+  constexpr bool B64 = sizeof(TB) == sizeof(D);
+  const int SB = B64 ? OZ_S64 : OZ_S;
+  const int gd = (int)((oz_plane_bytes(M) + EW - 1) / EW);
+  hipLaunchKernelGGL((oz_exp_kernel<Z, false>), dim3((M + 3) / 4, c.nE), dim3(256), 0, c.stream, c.zb(a), st, M, ea,
+                     es, c.st, check);
+  hipLaunchKernelGGL((oz_exp_kernel<TB, true>), dim3((M + 63) / 64, c.nE), dim3(256), 0, c.stream, Bsrc, st, M, eb,
+                     es, c.st, check);
+  hipLaunchKernelGGL((oz_digit_kernel<Z, false>), dim3(gd, c.nE), dim3(EW), 0, c.stream, c.zb(a), st, M, OZ_S, ea,
+                     es, Ap, st, c.st, check);
+  hipLaunchKernelGGL((oz_digit_kernel<TB, true>), dim3(gd, c.nE), dim3(EW), 0, c.stream, Bsrc, st, M, SB, eb, es,
+                     Bp, st, c.st, check);
+  const int tiles = (Mr / 32) * (Mr / 32);
+  if (B64)
+    hipLaunchKernelGGL((oz_gemm_kernel<OZ_S, OZ_S64>), dim3(tiles, c.nE), dim3(256), 0, c.stream, Ap, ea, Bp, eb, st,
+                       es, c.zb(out), st, M, cI, neg, c.st, check);
+  else
+    hipLaunchKernelGGL((oz_gemm_kernel<OZ_S, OZ_S>), dim3(tiles, c.nE), dim3(256), 0, c.stream, Ap, ea, Bp, eb, st, es,
+                       c.zb(out), st, M, cI, neg, c.st, check);
+  return hipGetLastError();
+}
+
 hipError_t gemm_zz(const Ctx &c, int a, int b, int out, double cI = 0.0, int neg = 0, int check = 1) {
+  if (c.oz) return gemm_oz<Z>(c, a, c.zb(b), out, cI, neg, check);
   hipLaunchKernelGGL((dd_gemm_kernel<Z, Z>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), c.zb(b),
                      (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
   return hipGetLastError();
@@ -585,6 +850,7 @@ hipError_t newton_corr(const Ctx &c, bool x0, int x, int r, int out, int check) 
 // products with the FP64 inverse X0 as the right factor
 hipError_t gemm_zd(const Ctx &c, int a, int out, double cI, int neg, int check) {
   const D *X = reinterpret_cast<const D *>(c.ws + c.sl.xi64);
+  if (c.oz) return gemm_oz<D>(c, a, X, out, cI, neg, check);
   hipLaunchKernelGGL((dd_gemm_kernel<Z, D>), dim3(c.gx(c.M), c.nE), dim3(GTHREADS), 0, c.stream, c.zb(a), X,
                      (const Z *)nullptr, c.zb(out), (int64_t)c.sl.bytes, c.M, cI, neg, c.st, check);
   return hipGetLastError();
@@ -690,6 +956,9 @@ hipError_t surfaces(const Ctx &c, const double *E, double eta, int both, int cel
 
 }  // namespace
 
+void decimation_products_set(int int8) { g_int8_products.store(int8 ? 1 : 0); }
+int decimation_products_get() { return g_int8_products.load(); }
+
 hipError_t launch_decimation(const StripDev &s, int side, const double *E, int nE, double eta, double tol,
                              int max_iter, knit_z *sigma, int32_t *iters, int32_t *pstatus, void *ws,
                              hipStream_t stream) {
@@ -703,7 +972,8 @@ hipError_t launch_decimation(const StripDev &s, int side, const double *E, int n
   const int both = side == 2;
   hipError_t err;
   // ---- every energy, cells of one slice
-  Ctx c{s, s.M, mfma_padded(s.M), nE, slab_of(s.M), slabs, st, nullptr, 0, stream};
+  // first pass: products on the INT8 matrix cores when enabled
+  Ctx c{s, s.M, mfma_padded(s.M), nE, slab_of(s.M), slabs, st, nullptr, 0, stream, g_int8_products.load()};
   hipLaunchKernelGGL(dec_reset_state_kernel, dim3((nE + 255) / 256), dim3(256), 0, stream, st, nE);
   hipLaunchKernelGGL(dec_init_kernel, dim3(EW_BLOCKS, nE), dim3(EW), 0, stream, s, side, c.ws, c.sl, c.st);
   if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -714,7 +984,11 @@ hipError_t launch_decimation(const StripDev &s, int side, const double *E, int n
   hipLaunchKernelGGL(dec_slot_assign_kernel, dim3(1), dim3(1), 0, stream, st, nE, st2, emap, fits ? 1 : 0);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (fits) {
-    Ctx c2{s, 2 * s.M, mfma_padded(2 * s.M), RETRY_SLOTS, slab_of(2 * s.M), slabs, st2, emap, 64, stream};
+    // retry pass (energies at slice eigenvalues, where the decimated couplings
+    // carry parts of size 1/eta beside small ones): double-double products on
+    // the vector units, accurate element by element rather than relative to
+    // each row's and column's largest entry
+    Ctx c2{s, 2 * s.M, mfma_padded(2 * s.M), RETRY_SLOTS, slab_of(2 * s.M), slabs, st2, emap, 64, stream, 0};
     hipLaunchKernelGGL(dec_init2_kernel, dim3(EW_BLOCKS, RETRY_SLOTS), dim3(EW), 0, stream, s, side, c2.ws, c2.sl,
                        c2.st);
     if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -53,6 +53,9 @@ hipError_t launch_decimation(const StripDev &s, int side, const double *E, int n
                              double tol, int max_iter, knit_z *sigma, int32_t *iters,
                              int32_t *pstatus, void *ws, hipStream_t stream);
 size_t decimation_workspace(int M, int nE);
+// Double-double products of the decimation: 1 on the INT8 matrix cores, 0 on the vector units.
+void decimation_products_set(int int8);
+int decimation_products_get();
 
 // Matrix-core FP64 inverses of n identity-padded [Mp][Mp] matrices (Mp = the
 // slice padding of M, at most 512), in place; natural-order inverses to out.

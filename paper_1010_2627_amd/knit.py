@@ -107,12 +107,19 @@ _lib.knit_sweep_tuning_set.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTun
 _lib.knit_sweep_tuning_get.restype = c_i32
 _lib.knit_sweep_tuning_get.argtypes = [c_i32, c_i32, ctypes.POINTER(KnitSweepTuning)]
 
+_lib.knit_set_selfenergy_products.restype = c_i32
+_lib.knit_set_selfenergy_products.argtypes = [c_i32]
+_lib.knit_get_selfenergy_products.restype = c_i32
+_lib.knit_get_selfenergy_products.argtypes = []
+KNIT_PRODUCTS_VECTOR, KNIT_PRODUCTS_INT8 = 0, 1
+
 _lib.knit_set_refine_threshold.restype = c_i32
 _lib.knit_set_refine_threshold.argtypes = [c_dbl]
 _lib.knit_get_refine_threshold.restype = c_dbl
 _lib.knit_get_refine_threshold.argtypes = []
 
-EXPORTED = ["knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
+EXPORTED = ["knit_set_selfenergy_products", "knit_get_selfenergy_products",
+            "knit_set_refine_threshold", "knit_get_refine_threshold", "knit_abi_version", "knit_status_string", "knit_lead_selfenergy_workspace",
             "knit_lead_selfenergy", "knit_rgf_sweep_workspace", "knit_rgf_sweep",
             "knit_transmission", "knit_ldos_workspace", "knit_ldos", "knit_sweep_tuning_set",
             "knit_sweep_tuning_get", "knit_gamma_factor", "knit_rgf_sweep_projected",
@@ -153,6 +160,15 @@ def knit_set_refine_threshold(threshold: float):
     """Largest ||I - A_n X0||_F (first residual of a slice's FP32 inverse) the refinement may
     start from before the problem is recomputed in FP64 (KNIT_P_FALLBACK)."""
     _check(_lib.knit_set_refine_threshold(float(threshold)), "knit_set_refine_threshold")
+
+
+def knit_set_selfenergy_products(mode: int):
+    """KNIT_PRODUCTS_INT8 (digit planes on the INT8 matrix cores) or KNIT_PRODUCTS_VECTOR."""
+    _check(_lib.knit_set_selfenergy_products(int(mode)), "knit_set_selfenergy_products")
+
+
+def knit_get_selfenergy_products() -> int:
+    return int(_lib.knit_get_selfenergy_products())
 
 
 def knit_get_refine_threshold() -> float:
