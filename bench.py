@@ -19,6 +19,12 @@ with the count of problems the refinement handed to FP64.  The headline
 `value` is the step throughput of the projected FP64 path, which meets the
 tolerance at every point; the others' figures sit beside it.
 
+Also timed, each once after an untimed call: the LDOS backward sweep, the
+transmission eigenvalues and Fano factor from the headline propagator, the
+injected densities and site currents, the conductance matrix with a side lead
+(the last three on every strip cut to 64 slices except the eigenvalues), and
+the knitting of a system with a hole and three leads.
+
 Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
 
@@ -284,6 +290,128 @@ def graph_leg(steps=3):
                          "flops_per_site_step": "8 norb D_t^2 (rank-norb update of the interface matrix)"}}
 
 
+def _timed_call(fn, stream, reps=1):
+    """Run fn once untimed, then `reps` times between two events on `stream`; (seconds per call, result)."""
+    import torch
+    out = fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps, out
+
+
+def _cut_table(b, knit, n_slices, ldos_width):
+    """The batch's problem table with every strip cut to its first n_slices slices; ldos_off packs
+    [L][ldos_width(strip)] per problem."""
+    host = b.probs.host.copy()
+    host["L"] = np.minimum(host["L"], n_slices)
+    w = np.array([ldos_width(b.strips[int(x)]) for x in host["strip"]], dtype=np.int64)
+    sizes = host["L"].astype(np.int64) * w
+    host["ldos_off"] = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    return knit.ProblemTable.from_host(host), host
+
+
+def next_rows(b, knit, G1Np, Tp, rankL, rankR, stream, n_slices=64):
+    """Timing of the three observables built on the sweep: transmission eigenvalues and the Fano
+    factor from the headline projected propagator (every problem), injected densities and site
+    currents, and the conductance matrix with one side lead (every problem cut to its first
+    n_slices slices).  Each carries its algorithmic flop count, the fraction of the FP64 peak
+    it reaches and a check that holds at any size."""
+    import torch
+    res = {}
+    Ms = np.array([b.strips[int(s)].M for s in b.probs.host["strip"]], dtype=np.float64)
+    P = b.P
+    rl, rr = rankL.astype(np.float64), rankR.astype(np.float64)
+
+    # transmission eigenvalues: t~ = P_N C_R (r_L x M x r_R), tau = t~^+ t~ on the smaller side,
+    # Householder tridiagonalisation (16/3 n^3), bisection not counted
+    n, m = np.minimum(rl, rr), np.maximum(rl, rr)
+    fl = float(np.sum(8.0 * rl * Ms * rr + 8.0 * n * n * m + 16.0 / 3.0 * n ** 3))
+    t, (tn, nch, T, fano) = _timed_call(lambda: b.transmission_eigenvalues(G1Np, stream), stream)
+    tn_h, T_h = tn.cpu().numpy(), T.cpu().numpy()
+    res["transmission_eigenvalues"] = {
+        "problems": P, "seconds": round(t, 4), "problems_per_s": P / t,
+        "tflops": fl / t / 1e12, "frac_of_fp64_peak": fl / t / 1e12 / PEAK_TFLOPS["fp64"],
+        "flops_per_problem": "8 r_L M r_R + 8 n^2 max(r_L, r_R) + 16/3 n^3, n = min(r_L, r_R)",
+        "kernel": "transmission_eigs_kernel (vector FP64, one workgroup per problem)",
+        "max_rel_dT_sum_Tn_vs_trace": float((np.abs(tn_h.sum(axis=1) - Tp) / np.maximum(1.0, Tp)).max()),
+        "max_rel_dT_trace_vs_headline": float((np.abs(T_h - Tp) / np.maximum(1.0, Tp)).max()),
+        "Tn_range": [float(tn_h.min()), float(tn_h.max())],
+        "fano_range": [float(fano.min()), float(fano.max())]}
+    del tn, nch, T, fano
+    progress(f"transmission eigenvalues: {t:.3f} s for {P} problems")
+
+    # injected densities and currents: forward inverse (8 M^3) and two rank-r propagations (16 M^2 r)
+    # per slice
+    sub, host = _cut_table(b, knit, n_slices, lambda s: s.W)
+    Lc = host["L"].astype(np.float64)
+    fl = float(np.sum((8.0 * Ms ** 3 + 16.0 * Ms ** 2 * rl) * Lc))
+    ws = torch.empty(max(knit._lib.knit_local_observables_workspace(
+        knit.strip_table(b.dstrips), len(b.dstrips), knit._ptr(sub.host), sub.P, 0), 1),
+        dtype=torch.uint8, device="cuda")
+    t, (blk, blk_off, jl, jt, st) = _timed_call(
+        lambda: knit.knit_local_observables(b.dstrips, sub, b.onsite, b.sigmaL, b.sigmaR, b.CL, 0, stream,
+                                            workspace=ws), stream)
+    del ws
+    # current conservation: the same current crosses every cut of a strip; the transverse inflows
+    # of a slice cancel
+    jl_h, jt_h = jl.cpu().numpy(), jt.cpu().numpy()
+    spread, tsum = 0.0, 0.0
+    for p in range(P):
+        o, L, W = int(host["ldos_off"][p]), int(host["L"][p]), b.strips[int(host["strip"][p])].W
+        cur = jl_h[o:o + L * W].reshape(L, W)[1:].sum(axis=1)
+        spread = max(spread, float((cur.max() - cur.min()) / max(1.0, abs(cur).max())))
+        tsum = max(tsum, float(np.abs(jt_h[o:o + L * W].reshape(L, W).sum(axis=1)).max() / max(1.0, abs(cur).max())))
+    res["local_observables"] = {
+        "slices_per_problem": f"min(L, {n_slices})", "problems": P, "slice_steps": int(Lc.sum()),
+        "seconds": round(t, 4), "slice_steps_per_s": float(Lc.sum()) / t,
+        "tflops": fl / t / 1e12, "frac_of_fp64_peak": fl / t / 1e12 / PEAK_TFLOPS["fp64"],
+        "flops_per_slice_step": "8 M^3 + 16 M^2 r (slice inverse, forward and reverse rank-r "
+                                "propagation; checkpoint recomputation not counted)",
+        "kernel": "lesser_mfma_kernel (FP64 MFMA)",
+        "problems_with_status": int((st.cpu().numpy() != 0).sum()),
+        "max_rel_spread_of_cut_currents": spread, "max_rel_transverse_inflow_sum": tsum}
+    del blk, jl, jt, st
+    progress(f"local observables: {t:.3f} s for {int(Lc.sum())} slice-steps")
+
+    # conductance matrix with one side lead on the middle slice of every cut strip (a lead of the
+    # strip's own cross section: Sigma_L and C_L of the same energy attached there)
+    sub, host = _cut_table(b, knit, n_slices, lambda s: s.M)
+    side = np.zeros((P, 1), dtype=knit.LEAD_DTYPE)
+    side["slice"][:, 0] = host["L"] // 2
+    side["sigma_off"][:, 0] = host["sigma_off"]
+    Lc = host["L"].astype(np.float64)
+    s_mid = (host["L"] // 2).astype(np.float64)
+    # forward and reverse inverses (16 M^3 per slice), one full-block inverse per lead slice (3),
+    # columns and rows of each lead carried from its slice to slice 0 (16 M^2 r each per slice)
+    fl = float(np.sum(16.0 * Ms ** 3 * Lc + 3 * 8.0 * Ms ** 3
+                      + 16.0 * Ms ** 2 * (rr * (Lc - 1) + rl * s_mid)))
+    ws = torch.empty(max(knit._lib.knit_conductance_matrix_workspace(
+        knit.strip_table(b.dstrips), len(b.dstrips), knit._ptr(sub.host), sub.P, 1, 0), 1),
+        dtype=torch.uint8, device="cuda")
+    t, (Tm, st) = _timed_call(
+        lambda: knit.knit_conductance_matrix(b.dstrips, sub, b.onsite, b.sigmaL, b.sigmaR, b.CL, b.CR, side,
+                                             b.sigmaL, b.CL, 0, stream, workspace=ws), stream)
+    del ws
+    Tm_h = Tm.cpu().numpy()
+    rs = np.abs(Tm_h.sum(axis=2) - Tm_h.sum(axis=1)).max(axis=1) / np.maximum(1.0, np.abs(Tm_h).max(axis=(1, 2)))
+    res["conductance_matrix"] = {
+        "slices_per_problem": f"min(L, {n_slices})", "leads": 3, "problems": P, "slice_steps": int(Lc.sum()),
+        "seconds": round(t, 4), "slice_steps_per_s": float(Lc.sum()) / t, "matrices_per_s": P / t,
+        "tflops": fl / t / 1e12, "frac_of_fp64_peak": fl / t / 1e12 / PEAK_TFLOPS["fp64"],
+        "flops_per_problem": "16 M^3 L + 24 M^3 + 16 M^2 (r_R (L-1) + r_X s_X)",
+        "kernel": "multiterminal_mfma_kernel (FP64 MFMA)",
+        "problems_with_status": int((st.cpu().numpy() != 0).sum()),
+        "max_rel_row_minus_column_sum": float(rs.max())}
+    del Tm, st
+    progress(f"conductance matrix: {t:.3f} s for {int(Lc.sum())} slice-steps")
+    return res
+
+
 def stated_form(b, knit, G1Np, ws_for, T64, wall64, nopen, steps, autotuned):
     """The uneven batch in its stated form: FP32 elimination with FP64 refinement on the projected
     path, the whole step (self-energies, broadening factors, projected sweep with its FP64 second
@@ -343,6 +471,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ldos", action="store_true", help="skip the LDOS (backward sweep) timing")
+    ap.add_argument("--no-observables", action="store_true",
+                    help="skip the timing of transmission eigenvalues, local observables and the conductance "
+                         "matrix")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline (projected FP64) step only: no other paths, no CPU baseline "
                          "(for profiler runs)")
@@ -354,7 +485,7 @@ def main():
                     help="first run one device copy of this size (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.headline_only:
-        args.no_mixed = args.no_ldos = args.no_cpu_baseline = True
+        args.no_mixed = args.no_ldos = args.no_cpu_baseline = args.no_observables = True
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "is described, not run)"}))
@@ -501,6 +632,11 @@ def main():
         del wsl, ld
         progress(f"ldos: {tl:.2f} s for {steps_l} slice-steps")
 
+    observables = None
+    if not args.no_observables:
+        rankR = b.problem_ranks()[1]
+        observables = next_rows(b, knit, G1Np, Tp, rankL, rankR, stream)
+
     achieved = flops_proj / twp / 1e12
     sweep_threads = knit.knit_sweep_tuning_get("fp64", knit.tuning_class((M + 31) // 32 * 32))["threads"]
     tr = MEASURED_TRAFFIC.get(args.workload)
@@ -581,6 +717,8 @@ def main():
     out["n_open_range"] = [int(nopen.min()), int(nopen.max())]
     if ldos_info is not None:
         out["ldos"] = ldos_info
+    if observables is not None:
+        out["observables"] = observables
     if tuning is not None:
         out["autotune"] = tuning
     if args.workload == "c3" and not args.headline_only:
