@@ -42,6 +42,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 
 #include "knit_internal.h"
 #include "knit_mfma.h"
@@ -373,6 +374,167 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32(cpx<RG> *X, cpx<RG> *S
   }
 }
 
+// LDS staging of the FP64 block products below.  The workgroup's waves form
+// WR x WC wave tiles of 64 x 32 (2 x 4 at 512 threads, 2 x 2 at 256), so one
+// group of tiles covers AR = 128 rows and BC = 32 WC columns; a k-chunk holds
+// KC slices of the group's A rows (AR x KC) and B columns (KC x BC).  Two
+// buffers, each its own LDS object, so that the compiler can tell a read of
+// one from a pending direct load into the other.
+template <int NT> struct UpdStage {
+  static constexpr int NW = NT / 64, WR = 2, WC = NW / WR;
+  static constexpr int KC = NT == 512 ? 16 : 8;
+  static constexpr int AR = 64 * WR, BC = 32 * WC;
+  static constexpr int A_EL = AR * KC, B_EL = KC * BC;
+};
+template <int NT> __device__ __forceinline__ cpx<double> *upd_stage0() {
+  __shared__ cpx<double> buf[UpdStage<NT>::A_EL + UpdStage<NT>::B_EL];
+  return buf;
+}
+template <int NT> __device__ __forceinline__ cpx<double> *upd_stage1() {
+  __shared__ cpx<double> buf[UpdStage<NT>::A_EL + UpdStage<NT>::B_EL];
+  return buf;
+}
+
+// Position of A element (row, k) of a chunk in its stage buffer: rows of KC
+// slots, the slot XOR-swizzled by the row so that the 16 rows one operand
+// read touches fall on 16 different 16-byte bank groups.
+template <int KC>
+__device__ __forceinline__ int upd_a_slot(int row, int k) {
+  return row * KC + (k ^ (KC == 16 ? (row & 15) : ((row >> 1) & 7)));
+}
+
+// Direct global -> LDS copy of 16 bytes per lane: lane i of the wave writes
+// dst + 16 i (dst wave-uniform).
+__device__ __forceinline__ void lds_copy16(const cpx<double> *src, cpx<double> *dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                   (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// tile_gemm_64x32 in FP64 with the operands staged through LDS: the
+// workgroup walks groups of WR x WC wave tiles; for each group the k-chunks
+// of its A rows and B columns are copied by direct global -> LDS loads into
+// one buffer while the waves multiply the chunk in the other.  Each wave
+// reads its operands from LDS and takes every output element's k-terms in
+// the same order as tile_gemm_64x32, so the results are bitwise the same.
+// The A rows of a group are read once per group instead of once per wave
+// tile, the B columns once per group instead of once per row tile.  Called
+// by the whole workgroup; K a multiple of 32.
+template <int NT, bool TO_S, bool ACC, bool NEG>
+__device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cpx<double> *S, int lds,
+                                                              const int *phys, int Mp, int rb1, int rn1, int rb2,
+                                                              int rn, int rh, int rhl, int cb1, int cn, int ch,
+                                                              int chl, int K, int arow, int acol, int krow0,
+                                                              int bshift) {
+  using U = UpdStage<NT>;
+  constexpr int KC = U::KC, AR = U::AR, BC = U::BC, WC = U::WC, NW = U::NW;
+  constexpr int A_INS = U::A_EL / 64 / NW, B_INS = U::B_EL / 64 / NW;   // copies per wave per chunk
+  constexpr int A_ROWS = 64 / KC;                                       // rows per A copy
+  // the row map lives in LDS: read it as LDS (a generic load would also wait
+  // for the direct loads in flight)
+  const __attribute__((address_space(3))) int *pl = (const __attribute__((address_space(3))) int *)phys;
+  auto rm = [=](int r) { return r < Mp ? pl[r] : r; };
+  const IdxMap rows{rb1, rn1, rb2, rn, rh, rhl}, cols{cb1, cn, 0, cn, ch, chl};
+  const int l = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave / WC, wc = wave % WC;
+  const int ngr = (rows.n + 1) / 2, ngc = (cols.n + WC - 1) / WC;
+  const int nch = K / KC;   // even
+  cpx<double> *st0 = upd_stage0<NT>(), *st1 = upd_stage1<NT>();
+  for (int g = 0; g < ngr * ngc; ++g) {
+    const int gr = g / ngc, gc = g % ngc;
+    const int ti = 2 * gr + wr, tj = WC * gc + wc;
+    const bool mine = ti < rows.n && tj < cols.n;
+    const int r0 = rows.at(ti < rows.n ? ti : 2 * gr, 64), c0 = cols.at(tj < cols.n ? tj : WC * gc, 32);
+    // this lane's source rows and columns of the group's copies (a tile
+    // outside the window takes the group's first tile: in bounds, unused)
+    int64_t asrc[A_INS];
+    bool aok[A_INS];
+#pragma unroll
+    for (int q = 0; q < A_INS; ++q) {
+      const int j = wave * A_INS + q, row = j * A_ROWS + l / KC, u = row / 64;
+      aok[q] = 2 * gr + u < rows.n;
+      const int p = l % KC, k = p ^ (KC == 16 ? (row & 15) : ((row >> 1) & 7));
+      asrc[q] = (int64_t)rm(arow + rows.at(aok[q] ? 2 * gr + u : 2 * gr, 64) + row % 64) * Mp + acol + k;
+    }
+    int bkrow[B_INS];
+    int64_t bcol[B_INS];
+#pragma unroll
+    for (int q = 0; q < B_INS; ++q) {
+      const int s = (wave * B_INS + q) * 64 + l, k = s / BC, col = s % BC, u = col / 32;
+      bkrow[q] = krow0 + k;
+      bcol[q] = cols.at(WC * gc + u < cols.n ? WC * gc + u : WC * gc, 32) + bshift + col % 32;
+    }
+    auto stage = [&](int chunk, cpx<double> *buf) {
+      const int kb = chunk * KC;
+#pragma unroll
+      for (int q = 0; q < A_INS; ++q)
+        if (aok[q]) lds_copy16(X + asrc[q] + kb, buf + (wave * A_INS + q) * 64);
+#pragma unroll
+      for (int q = 0; q < B_INS; ++q)
+        // B rows krow0 + k (k < K) are pivot rows, below Mp: always mapped
+        lds_copy16(X + (int64_t)pl[bkrow[q] + kb] * Mp + bcol[q], buf + U::A_EL + (wave * B_INS + q) * 64);
+    };
+    auto dst_of = [=](int r, int c) -> cpx<double> * {
+      if constexpr (TO_S) return S + (int64_t)(r0 + r) * lds + c0 + c;
+      else return X + (int64_t)rm(r0 + r) * Mp + c0 + c;
+    };
+    CTileRC<double, 4, 2> acc;
+    if (ACC && mine)
+      ctile_for_each_rc<double, 4, 2>(acc, [=](int r, int c, double &re, double &im) {
+        const cpx<double> v = *dst_of(r, c);
+        re = v.re;
+        im = v.im;
+      });
+    else
+      ctile_for_each_rc<double, 4, 2>(acc, [=](int, int, double &re, double &im) {
+        re = 0.0;
+        im = 0.0;
+      });
+    auto multiply = [&](const cpx<double> *buf) {
+      const cpx<double> *sa = buf, *sb = buf + U::A_EL;
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        cpx<double> a[4], b[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = sa[upd_a_slot<KC>(wr * 64 + 16 * i + (l & 15), 4 * ks + (l >> 4))];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sb[(4 * ks + (l >> 4)) * BC + wc * 32 + 16 * j + (l & 15)];
+        ctile_mma_rc<double, 4, 2>(acc, a, b);
+      }
+    };
+    stage(0, st0);
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < nch; c += 2) {
+      stage(c + 1, st1);
+      if (mine) multiply(st0);
+      __syncthreads();
+      if (c + 2 < nch) stage(c + 2, st0);
+      if (mine) multiply(st1);
+      __syncthreads();
+    }
+    if (mine)
+      ctile_for_each_rc<double, 4, 2>(acc, [=](int r, int c, double &re, double &im) {
+        *dst_of(r, c) = NEG ? cpx<double>{-re, -im} : cpx<double>{re, im};
+      });
+  }
+}
+
+// FP64 products go through the LDS-staged routine, FP32 ones through the
+// per-wave one.
+template <class RG, int NT, bool TO_S, bool ACC, bool NEG>
+__device__ __forceinline__ void tile_gemm_64x32_any(cpx<RG> *X, cpx<RG> *S, int lds, const int *phys, int Mp,
+                                                    int rb1, int rn1, int rb2, int rn, int rh, int rhl, int cb1,
+                                                    int cn, int ch, int chl, int K, int arow, int acol, int krow0,
+                                                    int bshift) {
+  if constexpr (std::is_same<RG, double>::value)
+    tile_gemm_64x32_lds<NT, TO_S, ACC, NEG>(X, S, lds, phys, Mp, rb1, rn1, rb2, rn, rh, rhl, cb1, cn, ch, chl, K,
+                                            arow, acol, krow0, bshift);
+  else
+    tile_gemm_64x32<RG, NT, TO_S, ACC, NEG>(X, S, lds, phys, Mp, rb1, rn1, rb2, rn, rh, rhl, cb1, cn, ch, chl, K,
+                                            arow, acol, krow0, bshift);
+}
+
 // The update inside an outer panel after its inner panel at k0:
 //   X[r, c] += sum_{k < 16} X[r, k0 + k] X[k0 + k, c]
 // for the 16-row tiles rows.at(i, 16) and 16-column tiles cols.at(j, 16).  A
@@ -514,7 +676,7 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
                                 0, K0, K0, K0, false, true);
       else {
         if (a64 + b64 > 0)
-          tile_gemm_64x32<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0,
+          tile_gemm_64x32_any<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0,
                                                      NOe / 32, 0, 0, NOe, 0, K0, K0, K0);
         if (n_below & 1)
           tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap(R - 32, 1), imap(0, NOe / 32), NOe, 0, K0, K0, K0, false,
@@ -525,7 +687,7 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     // when the panel width allows and there are at least two per wave)
     if (Mp > NOe) {
       if (NOe % 64 == 0 && (NOe / 64) * ocols.n >= 2 * NW)
-        tile_gemm_64x32<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
+        tile_gemm_64x32_any<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
                                                     ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, K0, K0, K0,
                                                     0);
       else
@@ -548,7 +710,7 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
       const int n64 = tall ? n32 / 2 : 0;
       const IdxMap rest = tall ? imap(R - 32, n32 & 1) : imap(0, n32, K0, NOe);
       if (n64 > 0)
-        tile_gemm_64x32<RG, NT, false, true, false>(X, nullptr, 0, rm.phys, Mp, 0, n64, 0, n64, K0, NOe, ocols.base1,
+        tile_gemm_64x32_any<RG, NT, false, true, false>(X, nullptr, 0, rm.phys, Mp, 0, n64, 0, n64, K0, NOe, ocols.base1,
                                                     ocols.n, ocols.hole, ocols.hole_len, NOe, 0, K0, K0, 0);
       if (rest.n > 0)
         tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, rest, ocols, NOe, 0, K0, K0, 0, true, false);
