@@ -418,13 +418,18 @@ __device__ __forceinline__ void lds_copy16(const cpx<double> *src, cpx<double> *
 // the same order as tile_gemm_64x32, so the results are bitwise the same.
 // The A rows of a group are read once per group instead of once per wave
 // tile, the B columns once per group instead of once per row tile.  Called
-// by the whole workgroup; K a multiple of 32.
+// by the whole workgroup; K a multiple of 32.  tail = 1: the last row tile
+// has only its first 32 rows (the others are neither read nor written).
+// A group reads all of its A rows and B columns before it writes any output,
+// and no other group writes them: the output may overwrite the group's own
+// A rows when the group spans every output column (WC tiles of 32 >= the
+// columns), or its B columns when it spans every output row.
 template <int NT, bool TO_S, bool ACC, bool NEG>
 __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cpx<double> *S, int lds,
                                                               const int *phys, int Mp, int rb1, int rn1, int rb2,
                                                               int rn, int rh, int rhl, int cb1, int cn, int ch,
                                                               int chl, int K, int arow, int acol, int krow0,
-                                                              int bshift) {
+                                                              int bshift, int tail) {
   using U = UpdStage<NT>;
   constexpr int KC = U::KC, AR = U::AR, BC = U::BC, WC = U::WC, NW = U::NW;
   constexpr int A_INS = U::A_EL / 64 / NW, B_INS = U::B_EL / 64 / NW;   // copies per wave per chunk
@@ -444,6 +449,7 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
     const int gr = g / ngc, gc = g % ngc;
     const int ti = 2 * gr + wr, tj = WC * gc + wc;
     const bool mine = ti < rows.n && tj < cols.n;
+    const int vrows = (tail && ti == rows.n - 1) ? 32 : 64;   // valid rows of this wave's tile
     const int r0 = rows.at(ti < rows.n ? ti : 2 * gr, 64), c0 = cols.at(tj < cols.n ? tj : WC * gc, 32);
     // this lane's source rows and columns of the group's copies (a tile
     // outside the window takes the group's first tile: in bounds, unused)
@@ -452,7 +458,7 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
 #pragma unroll
     for (int q = 0; q < A_INS; ++q) {
       const int j = wave * A_INS + q, row = j * A_ROWS + l / KC, u = row / 64;
-      aok[q] = 2 * gr + u < rows.n;
+      aok[q] = 2 * gr + u < rows.n && !(tail && 2 * gr + u == rows.n - 1 && row % 64 >= 32);
       const int p = l % KC, k = p ^ (KC == 16 ? (row & 15) : ((row >> 1) & 7));
       asrc[q] = (int64_t)rm(arow + rows.at(aok[q] ? 2 * gr + u : 2 * gr, 64) + row % 64) * Mp + acol + k;
     }
@@ -481,9 +487,14 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
     CTileRC<double, 4, 2> acc;
     if (ACC && mine)
       ctile_for_each_rc<double, 4, 2>(acc, [=](int r, int c, double &re, double &im) {
-        const cpx<double> v = *dst_of(r, c);
-        re = v.re;
-        im = v.im;
+        if (r < vrows) {
+          const cpx<double> v = *dst_of(r, c);
+          re = v.re;
+          im = v.im;
+        } else {
+          re = 0.0;
+          im = 0.0;
+        }
       });
     else
       ctile_for_each_rc<double, 4, 2>(acc, [=](int, int, double &re, double &im) {
@@ -515,7 +526,7 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
     }
     if (mine)
       ctile_for_each_rc<double, 4, 2>(acc, [=](int r, int c, double &re, double &im) {
-        *dst_of(r, c) = NEG ? cpx<double>{-re, -im} : cpx<double>{re, im};
+        if (r < vrows) *dst_of(r, c) = NEG ? cpx<double>{-re, -im} : cpx<double>{re, im};
       });
   }
 }
@@ -529,7 +540,7 @@ __device__ __forceinline__ void tile_gemm_64x32_any(cpx<RG> *X, cpx<RG> *S, int 
                                                     int bshift) {
   if constexpr (std::is_same<RG, double>::value)
     tile_gemm_64x32_lds<NT, TO_S, ACC, NEG>(X, S, lds, phys, Mp, rb1, rn1, rb2, rn, rh, rhl, cb1, cn, ch, chl, K,
-                                            arow, acol, krow0, bshift);
+                                            arow, acol, krow0, bshift, 0);
   else
     tile_gemm_64x32<RG, NT, TO_S, ACC, NEG>(X, S, lds, phys, Mp, rb1, rn1, rb2, rn, rh, rhl, cb1, cn, ch, chl, K,
                                             arow, acol, krow0, bshift);
@@ -664,17 +675,29 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     // ---- rank-NO update of the rest
     const int n_above = K0 / 32, n_below = (R - Mp) / 32;
     const IdxMap ocols = imap(0, (Mp - NOe) / 32, K0, NOe);
-    // (b) multipliers of the rows outside [K0, Mp): Sb = -X[r, K] T
-    // (64-row tiles where there are at least two per wave: the rows above P
-    // come in pairs of 32, the rows below Mp too except an odd last 32, which
-    // the 32 x 32 routine takes; otherwise 32 x 32 tiles throughout)
+    // (b) multipliers of the rows outside [K0, Mp): -X[r, K] T; (c) the
+    // update X[r, c] += X[r, K] X[P, c] of those rows and of the rows below P
+    // (with the old pivot rows X[P, c]); (d) the new pivot rows T X[P, c], for
+    // c outside the panel.
     constexpr int NW = NT / 64;
+    constexpr bool LDSP = std::is_same<RG, double>::value;
+    // FP64: the LDS-staged products.  (b) writes X[r, K] in place when one
+    // group spans the panel's columns; (d) writes X[P, c] in place after (c)
+    // has used the old rows (a group spans all of P).  No copies.
+    constexpr bool B_INPLACE = LDSP && UpdStage<NT>::BC >= NO;
     if (n_above + n_below > 0) {
       const int a64 = n_above / 2, b64 = n_below / 2;
-      if ((a64 + b64) * (NOe / 32) < 2 * NW)
+      if constexpr (B_INPLACE) {
+        tile_gemm_64x32_lds<NT, false, false, true>(X, nullptr, 0, rm.phys, Mp, 0, a64, Mp,
+                                                    a64 + b64 + (n_below & 1), 0, 0, K0, NOe / 32, 0, 0, NOe, 0, K0,
+                                                    K0, 0, n_below & 1);
+      } else if ((a64 + b64) * (NOe / 32) < 2 * NW) {
+        // (64-row tiles where there are at least two per wave: the rows above
+        // P come in pairs of 32, the rows below Mp too except an odd last 32,
+        // which the 32 x 32 routine takes; otherwise 32 x 32 tiles throughout)
         tile_gemm_window<RG, 2, NT>(X, Sb, NO, rm, imap2(0, n_above, Mp, n_above + n_below), imap(0, NOe / 32), NOe,
                                 0, K0, K0, K0, false, true);
-      else {
+      } else {
         if (a64 + b64 > 0)
           tile_gemm_64x32_any<RG, NT, true, false, true>(X, Sb, NO, rm.phys, Mp, 0, a64, Mp, a64 + b64, 0, 0, 0,
                                                      NOe / 32, 0, 0, NOe, 0, K0, K0, K0);
@@ -683,27 +706,31 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
                                   true);
       }
     }
-    // (d) new pivot rows: Sd = T X[P, c] for c outside the panel (64-row tiles
-    // when the panel width allows and there are at least two per wave)
-    if (Mp > NOe) {
-      if (NOe % 64 == 0 && (NOe / 64) * ocols.n >= 2 * NW)
-        tile_gemm_64x32_any<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
-                                                    ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, K0, K0, K0,
-                                                    0);
-      else
-        tile_gemm_window<RG, 2, NT>(X, Sd, Mp, rm, imap(0, NOe / 32), ocols, NOe, K0, K0, K0, 0, false, false);
+    if constexpr (!LDSP) {
+      // (d) into Sd (64-row tiles when the panel width allows and there are at
+      // least two per wave)
+      if (Mp > NOe) {
+        if (NOe % 64 == 0 && (NOe / 64) * ocols.n >= 2 * NW)
+          tile_gemm_64x32_any<RG, NT, true, false, false>(X, Sd, Mp, rm.phys, Mp, 0, NOe / 64, 0, NOe / 64, 0, 0,
+                                                      ocols.base1, ocols.n, ocols.hole, ocols.hole_len, NOe, K0, K0,
+                                                      K0, 0);
+        else
+          tile_gemm_window<RG, 2, NT>(X, Sd, Mp, rm, imap(0, NOe / 32), ocols, NOe, K0, K0, K0, 0, false, false);
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < (n_above + n_below) * 32 * NOe; e += blockDim.x) {
-      const int rr = e / NOe, c = e % NOe;
-      const int r = rr < n_above * 32 ? rr : Mp + (rr - n_above * 32);
-      X[(int64_t)rm(r) * Mp + K0 + c] = Sb[(int64_t)r * NO + c];
+    if constexpr (!B_INPLACE) {
+      for (int e = threadIdx.x; e < (n_above + n_below) * 32 * NOe; e += blockDim.x) {
+        const int rr = e / NOe, c = e % NOe;
+        const int r = rr < n_above * 32 ? rr : Mp + (rr - n_above * 32);
+        X[(int64_t)rm(r) * Mp + K0 + c] = Sb[(int64_t)r * NO + c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // (c) X[r, c] += X[r, K] X[P, c] (old pivot rows) for r outside P, c outside K:
-    // 64-row tiles where there are at least two per wave (K0 is a multiple of
-    // 64, so none straddles P), and the last 32 rows on their own when the
-    // count of 32-row tiles is odd (they follow P); otherwise 32 x 32 tiles
+    // (c): 64-row tiles where there are at least two per wave (K0 is a
+    // multiple of 64, so none straddles P), and the last 32 rows on their own
+    // when the count of 32-row tiles is odd (they follow P); otherwise 32 x 32
+    // tiles throughout
     if (Mp > NOe) {
       const int n32 = R / 32 - NOe / 32;
       const bool tall = (n32 / 2) * ocols.n >= 2 * NW;
@@ -716,10 +743,21 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
         tile_gemm_window<RG, 2, NT>(X, nullptr, 0, rm, rest, ocols, NOe, 0, K0, K0, 0, true, false);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NOe * Mp; e += blockDim.x) {
-      const int r = e / Mp, c = e % Mp;
-      if (c >= K0 && c < K0 + NOe) continue;
-      X[(int64_t)phys[K0 + r] * Mp + c] = Sd[(int64_t)r * Mp + c];
+    if constexpr (LDSP) {
+      // (d) in place: rows P = [K0, K0 + NOe) in 64-row tiles (the last one 32
+      // rows when NOe is an odd multiple of 32)
+      if (Mp > NOe) {
+        const int np = (NOe + 63) / 64;
+        tile_gemm_64x32_lds<NT, false, false, false>(X, nullptr, 0, rm.phys, Mp, K0, np, 0, np, 0, 0, ocols.base1,
+                                                     ocols.n, ocols.hole, ocols.hole_len, NOe, 0, K0, K0, 0,
+                                                     (NOe % 64) != 0);
+      }
+    } else {
+      for (int e = threadIdx.x; e < NOe * Mp; e += blockDim.x) {
+        const int r = e / Mp, c = e % Mp;
+        if (c >= K0 && c < K0 + NOe) continue;
+        X[(int64_t)phys[K0 + r] * Mp + c] = Sd[(int64_t)r * Mp + c];
+      }
     }
     __syncthreads();
   }
