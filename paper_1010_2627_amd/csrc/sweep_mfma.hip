@@ -380,12 +380,15 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32(cpx<RG> *X, cpx<RG> *S
 // KC slices of the group's A rows (AR x KC) and B columns (KC x BC).  Two
 // buffers, each its own LDS object, so that the compiler can tell a read of
 // one from a pending direct load into the other.
-template <int NT> struct UpdStage {
-  static constexpr int NW = NT / 64, WR = 2, WC = NW / WR;
+template <int NT, int WR_ = 2> struct UpdStage {
+  static constexpr int NW = NT / 64, WR = WR_, WC = NW / WR;
   static constexpr int KC = NT == 512 ? 16 : 8;
   static constexpr int AR = 64 * WR, BC = 32 * WC;
   static constexpr int A_EL = AR * KC, B_EL = KC * BC;
 };
+// (at 256 threads the 1 x 4 shape, 64 rows by 128 columns, needs the same
+// stage size as the 2 x 2 one: 64 x 8 + 8 x 128 = 128 x 8 + 8 x 64 elements)
+static_assert(UpdStage<256, 1>::A_EL + UpdStage<256, 1>::B_EL == UpdStage<256>::A_EL + UpdStage<256>::B_EL, "");
 template <int NT> __device__ __forceinline__ cpx<double> *upd_stage0() {
   __shared__ cpx<double> buf[UpdStage<NT>::A_EL + UpdStage<NT>::B_EL];
   return buf;
@@ -424,14 +427,14 @@ __device__ __forceinline__ void lds_copy16(const cpx<double> *src, cpx<double> *
 // and no other group writes them: the output may overwrite the group's own
 // A rows when the group spans every output column (WC tiles of 32 >= the
 // columns), or its B columns when it spans every output row.
-template <int NT, bool TO_S, bool ACC, bool NEG>
+template <int NT, bool TO_S, bool ACC, bool NEG, int WR_ = 2>
 __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cpx<double> *S, int lds,
                                                               const int *phys, int Mp, int rb1, int rn1, int rb2,
                                                               int rn, int rh, int rhl, int cb1, int cn, int ch,
                                                               int chl, int K, int arow, int acol, int krow0,
                                                               int bshift, int tail) {
-  using U = UpdStage<NT>;
-  constexpr int KC = U::KC, AR = U::AR, BC = U::BC, WC = U::WC, NW = U::NW;
+  using U = UpdStage<NT, WR_>;
+  constexpr int KC = U::KC, AR = U::AR, BC = U::BC, WC = U::WC, NW = U::NW, WR = U::WR;
   constexpr int A_INS = U::A_EL / 64 / NW, B_INS = U::B_EL / 64 / NW;   // copies per wave per chunk
   constexpr int A_ROWS = 64 / KC;                                       // rows per A copy
   // the row map lives in LDS: read it as LDS (a generic load would also wait
@@ -442,15 +445,15 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
   const int l = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave / WC, wc = wave % WC;
-  const int ngr = (rows.n + 1) / 2, ngc = (cols.n + WC - 1) / WC;
+  const int ngr = (rows.n + WR - 1) / WR, ngc = (cols.n + WC - 1) / WC;
   const int nch = K / KC;   // even
   cpx<double> *st0 = upd_stage0<NT>(), *st1 = upd_stage1<NT>();
   for (int g = 0; g < ngr * ngc; ++g) {
     const int gr = g / ngc, gc = g % ngc;
-    const int ti = 2 * gr + wr, tj = WC * gc + wc;
+    const int ti = WR * gr + wr, tj = WC * gc + wc;
     const bool mine = ti < rows.n && tj < cols.n;
     const int vrows = (tail && ti == rows.n - 1) ? 32 : 64;   // valid rows of this wave's tile
-    const int r0 = rows.at(ti < rows.n ? ti : 2 * gr, 64), c0 = cols.at(tj < cols.n ? tj : WC * gc, 32);
+    const int r0 = rows.at(ti < rows.n ? ti : WR * gr, 64), c0 = cols.at(tj < cols.n ? tj : WC * gc, 32);
     // this lane's source rows and columns of the group's copies (a tile
     // outside the window takes the group's first tile: in bounds, unused)
     int64_t asrc[A_INS];
@@ -458,9 +461,9 @@ __device__ __attribute__((noinline)) void tile_gemm_64x32_lds(cpx<double> *X, cp
 #pragma unroll
     for (int q = 0; q < A_INS; ++q) {
       const int j = wave * A_INS + q, row = j * A_ROWS + l / KC, u = row / 64;
-      aok[q] = 2 * gr + u < rows.n && !(tail && 2 * gr + u == rows.n - 1 && row % 64 >= 32);
+      aok[q] = WR * gr + u < rows.n && !(tail && WR * gr + u == rows.n - 1 && row % 64 >= 32);
       const int p = l % KC, k = p ^ (KC == 16 ? (row & 15) : ((row >> 1) & 7));
-      asrc[q] = (int64_t)rm(arow + rows.at(aok[q] ? 2 * gr + u : 2 * gr, 64) + row % 64) * Mp + acol + k;
+      asrc[q] = (int64_t)rm(arow + rows.at(aok[q] ? WR * gr + u : WR * gr, 64) + row % 64) * Mp + acol + k;
     }
     int bkrow[B_INS];
     int64_t bcol[B_INS];
@@ -684,11 +687,13 @@ __device__ int gj_two_level(cpx<RG> *X, int Mp, int R, int *phys, cpx<RG> *xchg,
     // FP64: the LDS-staged products.  (b) writes X[r, K] in place when one
     // group spans the panel's columns; (d) writes X[P, c] in place after (c)
     // has used the old rows (a group spans all of P).  No copies.
-    constexpr bool B_INPLACE = LDSP && UpdStage<NT>::BC >= NO;
+    // (at 256 threads with 128-wide panels the groups take the 1 x 4 shape)
+    constexpr int BWR = UpdStage<NT>::BC >= NO ? 2 : 1;
+    constexpr bool B_INPLACE = LDSP && UpdStage<NT, BWR>::BC >= NO;
     if (n_above + n_below > 0) {
       const int a64 = n_above / 2, b64 = n_below / 2;
       if constexpr (B_INPLACE) {
-        tile_gemm_64x32_lds<NT, false, false, true>(X, nullptr, 0, rm.phys, Mp, 0, a64, Mp,
+        tile_gemm_64x32_lds<NT, false, false, true, BWR>(X, nullptr, 0, rm.phys, Mp, 0, a64, Mp,
                                                     a64 + b64 + (n_below & 1), 0, 0, K0, NOe / 32, 0, 0, NOe, 0, K0,
                                                     K0, 0, n_below & 1);
       } else if ((a64 + b64) * (NOe / 32) < 2 * NW) {
