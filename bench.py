@@ -51,11 +51,11 @@ TOL_PER_CHANNEL = 1e-6
 # WRITE_SIZE counter runs, per workload, valid for the sweep source whose sha256
 # prefix is given; any other source reports null.
 MEASURED_TRAFFIC = {
-    "c4": {"sha": "2ee7222bf07fc1f5", "bytes": 4.5998e+13,
+    "c4": {"sha": "e1499ace1d798928", "bytes": 4.2371e+13,
            "profile": "profiles/sweep_fp64_c4_hbm_traffic.md",
            # executed matrix work and L2 behaviour of the same launch (same counter runs)
-           "counters": {"mfma_f64_flops_executed": 4.2922e+14, "mfma_busy_fraction": 0.449,
-                        "l2_hit_rate": 0.469}},
+           "counters": {"mfma_f64_flops_executed": 4.3128e+14, "mfma_busy_fraction": 0.492,
+                        "l2_hit_rate": 0.480}},
 }
 
 
