@@ -549,6 +549,106 @@ __device__ __forceinline__ void tile_gemm_64x32_any(cpx<RG> *X, cpx<RG> *S, int 
                                             arow, acol, krow0, bshift);
 }
 
+// D = A B (+ Add) in FP64 for plain row-major operands: rows r < Mr and
+// columns c < Nc (multiples of 32), K a multiple of 32.  The staging of
+// tile_gemm_64x32_lds (groups of 64 x 32 wave tiles, k-chunks copied by
+// direct global -> LDS loads into two buffers while the other is multiplied;
+// the last row tile may hold 32 rows), with every output element's k-terms
+// in ascending order from zero, as wg_gemm_mfma takes them: the results are
+// bitwise those of wg_gemm_mfma with a storing (or adding) epilogue.  D may
+// not overlap A or B.  Called by the whole workgroup.
+template <int NT>
+__device__ __attribute__((noinline)) void gemm_lds(int Mr, int Nc, int K, const cpx<double> *A, int64_t lda,
+                                                   const cpx<double> *B, int64_t ldb, cpx<double> *D, int64_t ldd,
+                                                   const cpx<double> *Add, int64_t ldadd) {
+  using U = UpdStage<NT>;
+  constexpr int KC = U::KC, BC = U::BC, WC = U::WC, WR = U::WR, NW = U::NW;
+  constexpr int A_INS = U::A_EL / 64 / NW, B_INS = U::B_EL / 64 / NW;
+  constexpr int A_ROWS = 64 / KC;
+  const int l = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave / WC, wc = wave % WC;
+  const int nrt = (Mr + 63) / 64, nct = Nc / 32;
+  const int ngr = (nrt + WR - 1) / WR, ngc = (nct + WC - 1) / WC;
+  const int nch = K / KC;   // even
+  cpx<double> *st0 = upd_stage0<NT>(), *st1 = upd_stage1<NT>();
+  for (int g = 0; g < ngr * ngc; ++g) {
+    const int gr = g / ngc, gc = g % ngc;
+    const int ti = WR * gr + wr, tj = WC * gc + wc;
+    const bool mine = ti < nrt && tj < nct;
+    const int r0 = 64 * ti, c0 = 32 * tj;
+    const int vrows = Mr - r0 < 64 ? Mr - r0 : 64;   // valid rows of this wave's tile
+    int64_t asrc[A_INS];
+    bool aok[A_INS];
+#pragma unroll
+    for (int q = 0; q < A_INS; ++q) {
+      const int j = wave * A_INS + q, row = j * A_ROWS + l / KC;
+      const int grow = 64 * WR * gr + row;   // A row of this copy
+      aok[q] = grow < Mr;                    // uniform over the copy (A_ROWS divides 32)
+      const int p = l % KC, k = p ^ (KC == 16 ? (row & 15) : ((row >> 1) & 7));
+      asrc[q] = (int64_t)(aok[q] ? grow : 0) * lda + k;
+    }
+    int bk[B_INS];
+    int64_t bcol[B_INS];
+#pragma unroll
+    for (int q = 0; q < B_INS; ++q) {
+      const int s = (wave * B_INS + q) * 64 + l, k = s / BC, col = s % BC;
+      const int gcol = 32 * WC * gc + col;
+      bk[q] = k;
+      bcol[q] = gcol < Nc ? gcol : col % 32;   // a column outside the window reads column tile 0
+    }
+    auto stage = [&](int chunk, cpx<double> *buf) {
+      const int kb = chunk * KC;
+#pragma unroll
+      for (int q = 0; q < A_INS; ++q)
+        if (aok[q]) lds_copy16(A + asrc[q] + kb, buf + (wave * A_INS + q) * 64);
+#pragma unroll
+      for (int q = 0; q < B_INS; ++q)
+        lds_copy16(B + (int64_t)(kb + bk[q]) * ldb + bcol[q], buf + U::A_EL + (wave * B_INS + q) * 64);
+    };
+    CTileRC<double, 4, 2> acc;
+    ctile_for_each_rc<double, 4, 2>(acc, [=](int, int, double &re, double &im) {
+      re = 0.0;
+      im = 0.0;
+    });
+    auto multiply = [&](const cpx<double> *buf) {
+      const cpx<double> *sa = buf, *sb = buf + U::A_EL;
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        cpx<double> a[4], b[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = sa[upd_a_slot<KC>(wr * 64 + 16 * i + (l & 15), 4 * ks + (l >> 4))];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = sb[(4 * ks + (l >> 4)) * BC + wc * 32 + 16 * j + (l & 15)];
+        ctile_mma_rc<double, 4, 2>(acc, a, b);
+      }
+    };
+    stage(0, st0);
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < nch; c += 2) {
+      stage(c + 1, st1);
+      if (mine) multiply(st0);
+      __syncthreads();
+      if (c + 2 < nch) stage(c + 2, st0);
+      if (mine) multiply(st1);
+      __syncthreads();
+    }
+    if (mine)
+      ctile_for_each_rc<double, 4, 2>(acc, [=](int r, int c, double &re, double &im) {
+        if (r < vrows) {
+          const int64_t o = (int64_t)(r0 + r) * ldd + c0 + c;
+          if (Add) {
+            const cpx<double> x = Add[(int64_t)(r0 + r) * ldadd + c0 + c];
+            D[o] = cpx<double>{x.re + re, x.im + im};
+          } else {
+            D[o] = cpx<double>{re, im};
+          }
+        }
+      });
+  }
+}
+
 // The update inside an outer panel after its inner panel at k0:
 //   X[r, c] += sum_{k < 16} X[r, k0 + k] X[k0 + k, c]
 // for the 16-row tiles rows.at(i, 16) and 16-column tiles cols.at(j, 16).  A
@@ -1653,16 +1753,12 @@ lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_
           U[i] = (a < M && c < r) ? ld_z(CL + pr.sigma_off + (int64_t)a * M + c) : C{0.0, 0.0};
         }
       } else if (dense) {
-        wg_gemm_mfma<double>(Mp, rp, Mp, Vd, Mp, Nprev, Mp, [&](int rr, int c, double &re, double &im) {
-          U[(int64_t)rr * Mp + c] = C{re, im};
-        });
+        gemm_lds<NT>(Mp, rp, Mp, Vd, Mp, Nprev, Mp, U, Mp, nullptr, 0);
       } else {
         gather_vg<double>(U, Nprev, s, Mp);
       }
       __syncthreads();
-      wg_gemm_mfma<double>(Mp, rp, Mp, gdst, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
-        Ndst[(int64_t)rr * Mp + c] = C{re, im};
-      });
+      gemm_lds<NT>(Mp, rp, Mp, gdst, Mp, U, Mp, Ndst, Mp, nullptr, 0);
       __syncthreads();
     };
     // per-row 2 Im sum_k Y[o,k] conj(Z[o,k]) summed over each site's orbitals into out[W]
@@ -1720,16 +1816,11 @@ lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_
         } else {
           // Q_n = N_n + g_n (V^+ Q_{n+1})
           if (dense)
-            wg_gemm_mfma<double>(Mp, rp, Mp, Vh, Mp, Qnext, Mp, [&](int rr, int c, double &re, double &im) {
-              U[(int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(Mp, rp, Mp, Vh, Mp, Qnext, Mp, U, Mp, nullptr, 0);
           else
             scatter_vdag<double>(U, Qnext, s, Mp, rp);
           __syncthreads();
-          wg_gemm_mfma<double>(Mp, rp, Mp, g, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
-            const int64_t o = (int64_t)rr * Mp + c;
-            Qn[o] = C{N[o].re + re, N[o].im + im};
-          });
+          gemm_lds<NT>(Mp, rp, Mp, g, Mp, U, Mp, Qn, Mp, N, Mp);
         }
         __syncthreads();
         // on-site blocks of A_L = Q Q^+
@@ -1747,9 +1838,7 @@ lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_
         // inflow into slice n+1 from slice n: 2 Im (V Q_n) . conj(Q_{n+1})
         if (n < L - 1) {
           if (dense)
-            wg_gemm_mfma<double>(Mp, rp, Mp, Vd, Mp, Qn, Mp, [&](int rr, int c, double &re, double &im) {
-              U[(int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(Mp, rp, Mp, Vd, Mp, Qn, Mp, U, Mp, nullptr, 0);
           else
             gather_vg<double>(U, Qn, s, Mp);
           __syncthreads();
@@ -1772,9 +1861,7 @@ lesser_mfma_kernel(StripTable tab, const knit_problem *probs, int P, const knit_
           }
           __syncthreads();
         }
-        wg_gemm_mfma<double>(Mp, rp, Mp, H0p, Mp, Qn, Mp, [&](int rr, int c, double &re, double &im) {
-          U[(int64_t)rr * Mp + c] = C{re, im};
-        });
+        gemm_lds<NT>(Mp, rp, Mp, H0p, Mp, Qn, Mp, U, Mp, nullptr, 0);
         __syncthreads();
         site_current(U, Qn, jt + (int64_t)n * W);
         C *t = Qn; Qn = Qnext; Qnext = t;
@@ -1958,9 +2045,7 @@ multiterminal_mfma_kernel(StripTable tab, const knit_problem *probs, int P, cons
       if (gr) {
         if (dense) {
           // X -= V^+ (gR V)
-          wg_gemm_mfma<double>(Mp, Mp, Mp, gr, Mp, Vd, Mp, [&](int rr, int c, double &re, double &im) {
-            U[(int64_t)rr * Mp + c] = C{re, im};
-          });
+          gemm_lds<NT>(Mp, Mp, Mp, gr, Mp, Vd, Mp, U, Mp, nullptr, 0);
           __syncthreads();
           wg_gemm_mfma<double>(Mp, Mp, Mp, Vh, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
             C &x = X[(int64_t)rr * Mp + c];
@@ -2055,14 +2140,10 @@ multiterminal_mfma_kernel(StripTable tab, const knit_problem *probs, int P, cons
             if (lslice[k] != n) continue;
             const int rp = rp_of(k);
             load_factor(k, false);
-            wg_gemm_mfma<double>(Mp, rp, Mp, Gnn, Mp, Cb, Mp, [&](int rr, int c, double &re, double &im) {
-              Yb[(int64_t)k * EE + (int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(Mp, rp, Mp, Gnn, Mp, Cb, Mp, Yb + (int64_t)k * EE, Mp, nullptr, 0);
             __syncthreads();
             load_factor(k, true);
-            wg_gemm_mfma<double>(rp, Mp, Mp, Cb, Mp, Gnn, Mp, [&](int rr, int c, double &re, double &im) {
-              Rb[(int64_t)k * EE + (int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(rp, Mp, Mp, Cb, Mp, Gnn, Mp, Rb + (int64_t)k * EE, Mp, nullptr, 0);
             __syncthreads();
           }
           // transmissions whose lower slice is n
@@ -2095,27 +2176,19 @@ multiterminal_mfma_kernel(StripTable tab, const knit_problem *probs, int P, cons
             C *Y = Yb + (int64_t)k * EE, *R = Rb + (int64_t)k * EE;
             // Y <- g^L_{n-1} (V^+ Y)
             if (dense)
-              wg_gemm_mfma<double>(Mp, rp, Mp, Vh, Mp, Y, Mp, [&](int rr, int c, double &re, double &im) {
-                U[(int64_t)rr * Mp + c] = C{re, im};
-              });
+              gemm_lds<NT>(Mp, rp, Mp, Vh, Mp, Y, Mp, U, Mp, nullptr, 0);
             else
               scatter_vdag<double>(U, Y, s, Mp, rp);
             __syncthreads();
-            wg_gemm_mfma<double>(Mp, rp, Mp, gl, Mp, U, Mp, [&](int rr, int c, double &re, double &im) {
-              Y[(int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(Mp, rp, Mp, gl, Mp, U, Mp, Y, Mp, nullptr, 0);
             __syncthreads();
             // R <- (R V) g^L_{n-1}
             if (dense)
-              wg_gemm_mfma<double>(rp, Mp, Mp, R, Mp, Vd, Mp, [&](int rr, int c, double &re, double &im) {
-                U2[(int64_t)rr * Mp + c] = C{re, im};
-              });
+              gemm_lds<NT>(rp, Mp, Mp, R, Mp, Vd, Mp, U2, Mp, nullptr, 0);
             else
               right_mul_v_blocks<double>(U2, R, s, vinv, Mp, rp);
             __syncthreads();
-            wg_gemm_mfma<double>(rp, Mp, Mp, U2, Mp, gl, Mp, [&](int rr, int c, double &re, double &im) {
-              R[(int64_t)rr * Mp + c] = C{re, im};
-            });
+            gemm_lds<NT>(rp, Mp, Mp, U2, Mp, gl, Mp, R, Mp, nullptr, 0);
             __syncthreads();
           }
         }
