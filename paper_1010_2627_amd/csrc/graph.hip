@@ -424,11 +424,16 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
           }
           if (small_inverse<M>(a, g) && tid == 0) sflag |= KNIT_P_SINGULAR;
         }
-        // phase 2: u = G[:, nb] H_{nb,i} (D x m), w = g H_{i,nb} G[nb, :] (m x D)
+        // phase 2: u = G[:, nb] H_{nb,i} (D x m), w = g H_{i,nb} G[nb, :] (m x D),
+        // with the new slot s folded in so that phase 3 is one uniform update:
+        // u's rows of s are the identity and w's columns of s are g, so that
+        // 0 + u w gives G[s, s] = g, G[s, :] = w, G[:, s] = u g
+        const int s0 = sl * M;
         for (int e = tid; e < Da * M; e += NT) {
           const int r = e / M, k = e % M;
           Z sum = {0.0, 0.0};
           for (int j = 0; j < np; ++j) sum = c_fma(Gc[j][r], shc[cur][j][k], sum);
+          if (r >= s0 && r < s0 + M) sum = Z{r - s0 == k ? 1.0 : 0.0, 0.0};
           su[r * MMAX + k] = sum;
         }
         for (int c = tid; c < Da; c += NT) {
@@ -440,17 +445,22 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
 #pragma unroll
             for (int l = 0; l < M; ++l) v[l] = c_fma(shr[cur][j][l], gv, v[l]);
           }
+          const bool cs = c >= s0 && c < s0 + M;
 #pragma unroll
           for (int k = 0; k < M; ++k) {
             Z sum = {0.0, 0.0};
 #pragma unroll
             for (int l = 0; l < M; ++l) sum = c_fma(g[k][l], v[l], sum);
+            if (cs) {
+#pragma unroll
+              for (int l = 0; l < M; ++l)
+                if (c - s0 == l) sum = g[k][l];
+            }
             sw[k * DM + c] = sum;
           }
         }
         __syncthreads();
-        // phase 3: G += u w outside the new slot, G[:, s] = u g, G[s, :] = w, G[s, s] = g
-        const int s0 = sl * M;
+        // phase 3: G <- (0 on the rows and columns of s, else G) + u w
         Z wc[CPT][M];   // w on the thread's columns
 #pragma unroll
         for (int b = 0; b < CPT; ++b)
@@ -468,25 +478,9 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
             const int c = tc + TC * b;
             if (rin && c < Da) {
               const bool cs = c >= s0 && c < s0 + M;
-              Z x = G.x[a][b];
-              if (rs || cs) {
-                x = Z{0.0, 0.0};
+              Z x = (rs || cs) ? Z{0.0, 0.0} : G.x[a][b];
 #pragma unroll
-                for (int k = 0; k < M; ++k)
-#pragma unroll
-                  for (int l = 0; l < M; ++l) {
-                    if (rs && cs) {
-                      if (r - s0 == k && c - s0 == l) x = g[k][l];
-                    } else if (rs) {
-                      if (r - s0 == k && l == 0) x = wc[b][k];
-                    } else {   // cs: (u g)[r][c - s0]
-                      if (c - s0 == l) x = c_fma(ur[k], g[k][l], x);
-                    }
-                  }
-              } else {
-#pragma unroll
-                for (int k = 0; k < M; ++k) x = c_fma(ur[k], wc[b][k], x);
-              }
+              for (int k = 0; k < M; ++k) x = c_fma(ur[k], wc[b][k], x);
               G.x[a][b] = x;
             }
           }
