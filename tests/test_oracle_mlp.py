@@ -2,8 +2,10 @@
 
 The reference (oracle.mlp) is checked against what fixes it independently: torch's own
 bfloat16 rounding, central finite differences of the exact (FP64, unrounded) network,
-and torch.optim.AdamW.  The sampler's placement and integration rules are checked on
-inputs whose answer is known in closed form.
+and torch.optim.AdamW.  Where the rounded network rounds is fixed by properties that
+the stated rounding places imply (BF16-valued activations and one-row gradients,
+invariance under moves inside a BF16 cell).  The sampler's placement and integration
+rules are checked on inputs whose answer is known in closed form.
 """
 
 import numpy as np
@@ -87,6 +89,66 @@ def test_rounded_network_stays_close_to_exact():
     for (a, _), (b, _) in zip(g64, g16):
         cos = float((a * b).sum() / np.linalg.norm(a) / np.linalg.norm(b))
         assert cos > 0.99
+
+
+def _bf16_exact(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return bool(np.all((a.view(np.uint32) & 0xFFFF) == 0))
+
+
+def _inside_cell(rng, a):
+    """A float32 array that rounds to the same BF16 values as a (a moved inside its cells)."""
+    a = OM.bf16_round(np.asarray(a, dtype=np.float32))
+    step = np.abs(a) * 2.0 ** -9                       # a quarter of a BF16 ulp (ulp = 2^-7 |a| or more)
+    return (a + step * rng.uniform(-1, 1, a.shape)).astype(np.float32)
+
+
+def test_rounding_sits_where_stated_forward():
+    """Where the forward pass rounds, fixed by properties rather than by retyping it:
+    stored activations are BF16 values; moving x or W inside their BF16 cells leaves the
+    logits bit for bit unchanged (so both are rounded before use); moving b inside its
+    BF16 cell changes them (so the bias is not rounded), as does moving x to the next BF16
+    value."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    params, x, _ = _tiny(5, sizes=(16, 32, 32, 8))
+    p32 = [(W.astype(np.float32), b.astype(np.float32)) for W, b in params]
+    x32 = x.astype(np.float32)
+    logits, cache = OM.forward(p32, x32)
+    assert all(_bf16_exact(X) for X in cache["X"])
+    assert not _bf16_exact(cache["Z"][0])               # pre-activations are not rounded
+    l2, _ = OM.forward(p32, _inside_cell(rng, x32))
+    assert np.array_equal(l2, logits)
+    l3, _ = OM.forward([(_inside_cell(rng, W), b) for W, b in p32], x32)
+    assert np.array_equal(l3, logits)
+    pc = [(W, OM.bf16_round(b)) for W, b in p32]            # biases at BF16 values, then moved
+    pb = [(W, (b * np.float32(1.0 + 2.0 ** -12)).astype(np.float32)) for W, b in pc]   # inside their cells
+    assert not np.array_equal(OM.forward(pb, x32)[0], OM.forward(pc, x32)[0])
+    xn = OM.bf16_round(x32)
+    xn[0, 0] = np.nextafter(xn[0, 0], np.float32(np.inf))
+    xn = OM.bf16_round(xn + np.sign(xn) * np.abs(xn) * np.float32(2.0 ** -7))
+    assert not np.array_equal(OM.forward(p32, xn)[0], logits)
+
+
+def test_rounding_sits_where_stated_backward():
+    """Where the backward pass rounds, from the structure of one-row gradients: with a batch
+    of one, db_l is dZ_l and dW_l the outer product dZ_l X_{l-1}, so db_l must be BF16
+    values (rounded after the GELU derivative is applied, not before) and dW_l their exact
+    products with the stored activations (a BF16 x BF16 product is exact in FP32); and
+    moving W inside its BF16 cells leaves every gradient bit for bit
+    unchanged (the backward uses the rounded weights)."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    params, x, q = _tiny(6, sizes=(16, 32, 32, 8))
+    p32 = [(W.astype(np.float32), b.astype(np.float32)) for W, b in params]
+    x1, q1 = x[:1].astype(np.float32), q[:1].astype(np.float32)
+    _, cache = OM.forward(p32, x1)
+    grads = OM.backward(p32, cache, q1)
+    for li, (dW, db) in enumerate(grads):
+        assert _bf16_exact(db), li
+        assert np.array_equal(dW, np.outer(db, cache["X"][li]).astype(np.float32)), li
+    pw = [(_inside_cell(rng, W), b) for W, b in p32]
+    _, c2 = OM.forward(pw, x1)
+    for (a, b), (c, d) in zip(grads, OM.backward(pw, c2, q1)):
+        assert np.array_equal(a, c) and np.array_equal(b, d)
 
 
 # ---------------------------------------------------------------- sampler host logic
