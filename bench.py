@@ -290,6 +290,42 @@ def graph_leg(steps=3):
                          "flops_per_site_step": "8 norb D_t^2 (rank-norb update of the interface matrix)"}}
 
 
+# Knitting with an interface wider than the register mode holds (the matrix in the workgroup's
+# slab): a 96 x 96 sample with a 30 x 16 hole, flux 0.01, disorder U[-0.5, 0.5], leads on both
+# ends, 256 energies; site by site against the automatic groups of sites per step.
+GRAPH_WIDE_WORKLOAD = dict(W=96, L=96, hole=(30, 40, 60, 56), flux=0.01, w=1.0, P=256,
+                           desc="square-lattice sample 96 x 96 with a 30 x 16 hole, flux 0.01 per plaquette, "
+                                "disorder U[-0.5,0.5], leads on both ends, 256 energies, seeded synthetic lead "
+                                "self-energies")
+
+
+def graph_wide_leg(steps=2):
+    import torch
+    from paper_1010_2627_amd import inputs, workload
+    c = GRAPH_WIDE_WORKLOAD
+    W, L, P = c["W"], c["L"], c["P"]
+    g = inputs.square_lattice_graph(inputs.rectangle_with_hole(L, W, c["hole"]), flux=c["flux"])
+    idx = {s: i for i, s in enumerate(g.coords)}
+    leads = [[idx[(0, y)] for y in range(W) if (0, y) in idx], [idx[(L - 1, y)] for y in range(W) if (L - 1, y) in idx]]
+    E = inputs.midpoint_grid(-3.5, 3.5, P)
+    sig = [inputs.synthetic_sigma(len(l), P, seed=3101 + k, rank=max(1, len(l) // 2)) for k, l in enumerate(leads)]
+    ons = inputs.graph_disorder(g, c["w"], seed=20102627)
+    stream = torch.cuda.current_stream()
+    out, Ts = {"workload": c["desc"], "sites": g.N}, []
+    for name, block in (("site_by_site", None), ("automatic_groups", 0)):
+        b = workload.GraphBatch(g, leads, E, ons, sig, block=block)
+        inf = b.info
+        ws = torch.empty(b.plan.workspace(P), dtype=torch.uint8, device="cuda")
+        t, (T, _, st) = _timed_call(lambda: b.run(ws=ws), stream, steps)
+        Ts.append(T.cpu().numpy())
+        out[name] = {"sites_per_step": inf["block"], "interface_dim_max": inf["dim"], "steps": inf["n_steps"],
+                     "seconds_per_launch": round(t, 5), "site_steps_per_s": (g.N - len(leads[0])) * P / t,
+                     "problems_with_status": int((st.cpu().numpy() != 0).sum())}
+    out["speedup"] = out["site_by_site"]["seconds_per_launch"] / out["automatic_groups"]["seconds_per_launch"]
+    out["max_dT_groups_vs_site_by_site"] = float(np.abs(Ts[1] - Ts[0]).max())
+    return out
+
+
 def _timed_call(fn, stream, reps=1):
     """Run fn once untimed, then `reps` times between two events on `stream`; (seconds per call, result)."""
     import torch
@@ -497,7 +533,9 @@ def main():
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     if args.graph_only:
-        print(json.dumps(graph_leg()))
+        leg = graph_leg()
+        leg["wide_interface"] = graph_wide_leg()
+        print(json.dumps(leg))
         return
     if cfg["kind"] == "sampler":
         sampler_bench(args, cfg)
@@ -727,6 +765,7 @@ def main():
         progress("c3 stated form done")
     if not args.headline_only:
         out["graph_knitting"] = graph_leg()
+        out["graph_knitting"]["wide_interface"] = graph_wide_leg()
         progress("graph knitting done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, b)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KNIT_ABI_VERSION 3
+#define KNIT_ABI_VERSION 4
 #define KNIT_MAX_STRIPS 64     /* strip classes per batch */
 #define KNIT_MAX_M 1024        /* largest slice dimension */
 #define KNIT_MAX_NORB 4        /* largest orbitals-per-site */

@@ -70,6 +70,8 @@ typedef struct knit_graph_info {
   int64_t nnz;           /* hopping blocks (directed edges) */
   double update_flops;   /* sum over steps of 8 norb D_t^2, D_t the dimension updated at step t */
   double update_bytes;   /* sum over steps of 32 D_t^2: one read and one write of the updated block */
+  int32_t block;         /* sites added per step (1: site by site; see knit_graph_plan_create_blocked) */
+  int32_t reserved;
 } knit_graph_info;
 
 /* One problem: an energy, its on-site blocks and its self-energies. */
@@ -107,6 +109,37 @@ typedef struct knit_graph_problem {
 int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
                            int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
                            knit_graph_plan **plan);
+/*
+ * The same, adding `block` sites per step (section 1: a group of sites, like a
+ * layer, joins the system by the same Dyson equation with the group's block
+ * H_bb, its internal hoppings included, in place of H_ii).  The sites are
+ * grouped once on the host: each lead's sites `block` at a time in the lead's
+ * order, the other sites `block` at a time in the knitting order (the order
+ * knit_graph_plan_create would take); a last group with fewer sites is padded
+ * with orbitals that couple to nothing and have E - H = 1, which leave every
+ * other entry of G unchanged.  The groups are then knitted as the sites of a
+ * graph with block * norb orbitals per site.  T and the lead block of G have
+ * the same meaning and layout as for knit_graph_plan_create; the work per
+ * step is a rank-(block * norb) update, which spreads one step's fixed
+ * latency over `block` sites.
+ *   block   1 .. KNIT_MAX_NORB / norb, dividing every lead's nsite
+ *           (KNIT_E_ARG otherwise); 1 gives knit_graph_plan_create's plan.
+ *           0: automatic.  1 when the site-by-site interface dimension is
+ *           at most 128 (the matrix stays in registers, where a step's cost
+ *           grows with the orbitals it couples and groups gain nothing);
+ *           above, where every step passes over the matrix in memory, the
+ *           valid block with block * norb closest to 3 (the larger of two
+ *           equally close) whose plan exists, else 1.
+ * info of a blocked plan: nsite, norb and nnz are the system's; max_slots,
+ * dim, max_pairs, n_steps, update_flops and update_bytes count groups, the
+ * steps and the updates the device makes; block is the one chosen.
+ * knit_graph_plan_order returns the site order the groups were taken from.
+ * knit_graph_workspace grows by the groups' on-site blocks for every problem,
+ * (P * n_groups + n_group_edges) * (block * norb)^2 knit_z.
+ */
+int knit_graph_plan_create_blocked(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
+                                   int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
+                                   int32_t block, knit_graph_plan **plan);
 int knit_graph_plan_info(const knit_graph_plan *plan, knit_graph_info *info);
 /* The site order the plan knits in (host [nsite]). */
 int knit_graph_plan_order(const knit_graph_plan *plan, int32_t *order);

@@ -29,6 +29,7 @@
 // workgroup's slab (L2-resident for moderate D).
 
 #include <algorithm>
+#include <cstdlib>
 #include <functional>
 #include <new>
 #include <queue>
@@ -41,10 +42,14 @@
 // ---------------------------------------------------------------- host plan
 
 struct knit_graph_plan {
-  int N = 0, m = 0, K = 0;
+  int N = 0, m = 0, K = 0;      // sites, orbitals per site (per group in a blocked plan), leads
   std::vector<int32_t> order;   // full knitting order (lead 0's sites first)
   std::vector<int32_t> image;   // device image of the plan (int32 words)
   knit_graph_info info{};
+  // blocked plans: groups of `block` sites knitted as one site of block * norb
+  // orbitals; `gmap` (device words) says how the groups' blocks are gathered
+  int block = 1;
+  std::vector<int32_t> gmap;
 };
 
 namespace knit {
@@ -657,6 +662,73 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
   }
 }
 
+// ---------------------------------------------------------------- blocked plans
+
+// words of a blocked plan's group map (header, then the arrays it points at)
+enum { GM_NC, GM_MB, GM_B, GM_M, GM_NNZ, GM_MEM, GM_INPTR, GM_IN, GM_EPTR, GM_E, GM_WORDS = 16 };
+
+// Hopping blocks of the group graph: block (a, b) of group edge (g, h) is the
+// hopping block from member a of g to member b of h, zero where they are not
+// coupled.  One element per thread, grid-strided.
+__global__ void __launch_bounds__(256) group_hop_kernel(const int32_t *gm, const knit_z *hop, knit_z *ghop) {
+  const int nnzc = gm[GM_NNZ], MB = gm[GM_MB], m = gm[GM_M];
+  const int32_t *eptr = gm + gm[GM_EPTR], *et = gm + gm[GM_E];
+  const int64_t n = (int64_t)nnzc * MB * MB;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int ec = (int)(i / (MB * MB)), r = (int)(i / MB % MB), c = (int)(i % MB);
+    const int a = r / m, bq = c / m;
+    knit_z v{0.0, 0.0};
+    for (int q = eptr[ec]; q < eptr[ec + 1]; ++q)
+      if (et[3 * q] == a && et[3 * q + 1] == bq) v = hop[(int64_t)et[3 * q + 2] * m * m + (r % m) * m + c % m];
+    ghop[i] = v;
+  }
+}
+
+// On-site blocks of the groups for every problem: the members' on-site blocks
+// on the diagonal, the hoppings between members off it, E - H = 1 (and no
+// coupling) on padding orbitals; and the problem table that points at them.
+__global__ void __launch_bounds__(256) group_onsite_kernel(const int32_t *gm, const knit_graph_problem *probs, int P,
+                                                           const knit_z *hop, const knit_z *onsite, knit_z *gons,
+                                                           knit_graph_problem *gprobs) {
+  const int Nc = gm[GM_NC], MB = gm[GM_MB], b = gm[GM_B], m = gm[GM_M];
+  const int32_t *mem = gm + gm[GM_MEM], *inptr = gm + gm[GM_INPTR], *it = gm + gm[GM_IN];
+  const int64_t per = (int64_t)Nc * MB * MB, n = per * P;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i / per);
+    const int64_t j = i % per;
+    const int g = (int)(j / (MB * MB)), r = (int)(j / MB % MB), c = (int)(j % MB);
+    const int a = r / m, bq = c / m;
+    const knit_graph_problem pr = probs[p];
+    knit_z v{0.0, 0.0};
+    if (a == bq) {
+      const int s = mem[(int64_t)g * b + a];
+      if (s >= 0) v = onsite[pr.onsite_off + (int64_t)s * m * m + (r % m) * m + c % m];
+      else if (r == c) v = knit_z{pr.E - 1.0, 0.0};
+    } else {
+      for (int q = inptr[g]; q < inptr[g + 1]; ++q)
+        if (it[3 * q] == a && it[3 * q + 1] == bq) v = hop[(int64_t)it[3 * q + 2] * m * m + (r % m) * m + c % m];
+    }
+    gons[i] = v;
+    if (j == 0) {
+      knit_graph_problem q = pr;
+      q.onsite_off = (int64_t)p * per;
+      gprobs[p] = q;
+    }
+  }
+}
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+// workspace bytes of a blocked plan's gathered blocks (group map, hopping
+// blocks, per-problem on-site blocks, problem table)
+size_t group_bytes(const knit_graph_plan *p, int P) {
+  if (p->block <= 1) return 0;
+  const int32_t *gm = p->gmap.data();
+  const size_t bb = (size_t)gm[GM_MB] * gm[GM_MB] * sizeof(knit_z);
+  return round256(p->gmap.size() * 4) + round256((size_t)gm[GM_NNZ] * bb) + round256((size_t)P * gm[GM_NC] * bb) +
+         round256((size_t)P * sizeof(knit_graph_problem));
+}
+
 constexpr int GRAPH_MAX_GRID = 1024;
 
 int64_t slab_elems_of(int D, int LD, bool reg) {
@@ -675,11 +747,13 @@ size_t image_bytes(const knit_graph_plan *p) { return (p->image.size() * 4 + 255
 
 using namespace knit;
 
-extern "C" int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
-                                      int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
-                                      knit_graph_plan **plan) {
-  if (!plan) return KNIT_E_ARG;
-  *plan = nullptr;
+namespace knit {
+namespace {
+
+// Validates the graph and the leads, fixes the order and replays it (slots,
+// interface, step records) into *pl.  Nothing is kept on failure.
+int build_plan(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col, int32_t n_leads,
+               const knit_graph_lead *leads, const int32_t *order, knit_graph_plan *pl) {
   if (nsite < 1 || norb < 1 || norb > KNIT_MAX_NORB || !row_ptr || !leads || n_leads < 1 ||
       n_leads > KNIT_GRAPH_MAX_LEADS)
     return KNIT_E_ARG;
@@ -836,8 +910,6 @@ extern "C" int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t
   const int D = max_slots * m, LD = nls * m;
   if (D > KNIT_GRAPH_MAX_DIM) return KNIT_E_UNSUPPORTED;
 
-  knit_graph_plan *pl = new (std::nothrow) knit_graph_plan();
-  if (!pl) return KNIT_E_ARG;
   pl->N = N;
   pl->m = m;
   pl->K = K;
@@ -908,7 +980,196 @@ extern "C" int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t
   in.nnz = nnz;
   in.update_flops = flops;
   in.update_bytes = bytes;
-  *plan = pl;
+  in.block = 1;
+  return KNIT_OK;
+}
+
+}  // namespace
+}  // namespace knit
+
+extern "C" int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
+                                      int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
+                                      knit_graph_plan **plan) {
+  return knit_graph_plan_create_blocked(nsite, norb, row_ptr, col, n_leads, leads, order, 1, plan);
+}
+
+namespace knit {
+namespace {
+
+// The group plan of a validated site plan: groups of b sites (each lead's
+// sites b at a time in lead order, the others b at a time in the site order),
+// the graph of the groups with their member-to-member hops, and the plan of
+// that graph with b * norb orbitals per group, knitted in the order in which
+// the groups' first members come in the site order.
+int build_blocked(const knit_graph_plan &fine, const int32_t *row_ptr, const int32_t *col, int K,
+                  const knit_graph_lead *leads, int b, knit_graph_plan *out) {
+  const int N = fine.N, m = fine.m, MB = b * m;
+  std::vector<int> grp(N, -1), gpos(N, -1);
+  std::vector<int32_t> members;   // [groups][b]: member sites, -1 for padding
+  auto new_group = [&]() {
+    members.insert(members.end(), b, -1);
+    return (int)(members.size() / b) - 1;
+  };
+  auto put = [&](int g, int a, int s) {
+    grp[s] = g;
+    gpos[s] = a;
+    members[(size_t)g * b + a] = s;
+  };
+  std::vector<std::vector<int32_t>> lgroups(K);
+  for (int k = 0; k < K; ++k)
+    for (int q = 0; q < leads[k].nsite; ++q) {
+      if (q % b == 0) lgroups[k].push_back(new_group());
+      put(lgroups[k].back(), q % b, leads[k].sites[q]);
+    }
+  int cur = -1, fill = b;
+  for (int s : fine.order) {
+    if (grp[s] >= 0) continue;
+    if (fill == b) {
+      cur = new_group();
+      fill = 0;
+    }
+    put(cur, fill++, s);
+  }
+  const int Nc = (int)(members.size() / b);
+  std::vector<int32_t> gorder;
+  std::vector<char> seen(Nc, 0);
+  for (int s : fine.order)
+    if (!seen[grp[s]]) {
+      seen[grp[s]] = 1;
+      gorder.push_back(grp[s]);
+    }
+  std::vector<int32_t> grow(Nc + 1, 0), gcol, eptr{0}, etri, inptr{0}, intri;
+  for (int g = 0; g < Nc; ++g) {
+    std::vector<int32_t> nb;
+    for (int a = 0; a < b; ++a) {
+      const int s = members[(size_t)g * b + a];
+      if (s < 0) continue;
+      for (int e = row_ptr[s]; e < row_ptr[s + 1]; ++e) {
+        const int h = grp[col[e]];
+        if (h == g) {
+          intri.push_back(a);
+          intri.push_back(gpos[col[e]]);
+          intri.push_back(e);
+        } else {
+          nb.push_back(h);
+        }
+      }
+    }
+    inptr.push_back((int32_t)(intri.size() / 3));
+    std::sort(nb.begin(), nb.end());
+    nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+    for (int h : nb) {
+      gcol.push_back(h);
+      for (int a = 0; a < b; ++a) {
+        const int s = members[(size_t)g * b + a];
+        if (s < 0) continue;
+        for (int e = row_ptr[s]; e < row_ptr[s + 1]; ++e)
+          if (grp[col[e]] == h) {
+            etri.push_back(a);
+            etri.push_back(gpos[col[e]]);
+            etri.push_back(e);
+          }
+      }
+      eptr.push_back((int32_t)(etri.size() / 3));
+    }
+    grow[g + 1] = (int32_t)gcol.size();
+  }
+  std::vector<knit_graph_lead> gl(K);
+  for (int k = 0; k < K; ++k) gl[k] = knit_graph_lead{(int32_t)lgroups[k].size(), 0, lgroups[k].data()};
+  const int rc = build_plan(Nc, MB, grow.data(), gcol.empty() ? nullptr : gcol.data(), K, gl.data(), gorder.data(),
+                            out);
+  if (rc != KNIT_OK) return rc;
+  out->order = fine.order;
+  out->block = b;
+  out->info.nsite = N;
+  out->info.norb = m;
+  out->info.nnz = fine.info.nnz;
+  out->info.block = b;
+  std::vector<int32_t> &gm = out->gmap;
+  gm.assign(GM_WORDS, 0);
+  gm[GM_NC] = Nc;
+  gm[GM_MB] = MB;
+  gm[GM_B] = b;
+  gm[GM_M] = m;
+  gm[GM_NNZ] = (int32_t)gcol.size();
+  gm[GM_MEM] = (int32_t)gm.size();
+  gm.insert(gm.end(), members.begin(), members.end());
+  gm[GM_INPTR] = (int32_t)gm.size();
+  gm.insert(gm.end(), inptr.begin(), inptr.end());
+  gm[GM_IN] = (int32_t)gm.size();
+  gm.insert(gm.end(), intri.begin(), intri.end());
+  gm[GM_EPTR] = (int32_t)gm.size();
+  gm.insert(gm.end(), eptr.begin(), eptr.end());
+  gm[GM_E] = (int32_t)gm.size();
+  gm.insert(gm.end(), etri.begin(), etri.end());
+  return KNIT_OK;
+}
+
+}  // namespace
+}  // namespace knit
+
+extern "C" int knit_graph_plan_create_blocked(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
+                                              int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
+                                              int32_t block, knit_graph_plan **plan) {
+  if (!plan) return KNIT_E_ARG;
+  *plan = nullptr;
+  if (block < 0) return KNIT_E_ARG;
+  knit_graph_plan *fine = new (std::nothrow) knit_graph_plan();
+  if (!fine) return KNIT_E_ARG;
+  const int rc = build_plan(nsite, norb, row_ptr, col, n_leads, leads, order, fine);
+  if (rc != KNIT_OK || block == 1) {
+    if (rc == KNIT_OK) *plan = fine;
+    else delete fine;
+    return rc;
+  }
+  auto fits = [&](int b) {
+    if (b * norb > KNIT_MAX_NORB) return false;
+    for (int k = 0; k < n_leads; ++k)
+      if (leads[k].nsite % b) return false;
+    return true;
+  };
+  if (block > 1) {
+    if (!fits(block)) {
+      delete fine;
+      return KNIT_E_ARG;
+    }
+    knit_graph_plan *bp = new (std::nothrow) knit_graph_plan();
+    const int rb = bp ? build_blocked(*fine, row_ptr, col, n_leads, leads, block, bp) : KNIT_E_ARG;
+    delete fine;
+    if (rb != KNIT_OK) {
+      delete bp;
+      return rb;
+    }
+    *plan = bp;
+    return KNIT_OK;
+  }
+  // Automatic.  With the interface in registers a step's cost grows with the
+  // orbitals it couples, so groups gain nothing there: site by site.  With the
+  // interface in the slab every step is a pass over it in memory, which groups
+  // share; the serial group inverse grows with the group, so groups of about
+  // three orbitals come first, then the larger of two equally close sizes.
+  if (reg_mode(fine->info.dim)) {
+    *plan = fine;
+    return KNIT_OK;
+  }
+  std::vector<int> cand;
+  for (int b = 2; b * norb <= KNIT_MAX_NORB; ++b)
+    if (fits(b)) cand.push_back(b);
+  std::sort(cand.begin(), cand.end(), [&](int x, int y) {
+    const int dx = std::abs(x * norb - 3), dy = std::abs(y * norb - 3);
+    return dx != dy ? dx < dy : x > y;
+  });
+  for (int b : cand) {
+    knit_graph_plan *bp = new (std::nothrow) knit_graph_plan();
+    if (!bp) break;
+    if (build_blocked(*fine, row_ptr, col, n_leads, leads, b, bp) == KNIT_OK) {
+      delete fine;
+      *plan = bp;
+      return KNIT_OK;
+    }
+    delete bp;
+  }
+  *plan = fine;
   return KNIT_OK;
 }
 
@@ -954,7 +1215,8 @@ int graph_grid(int P, int D) {
 extern "C" size_t knit_graph_workspace(const knit_graph_plan *plan, int32_t P) {
   if (!plan || P < 1) return 0;
   const int D = plan->info.dim, LD = plan->info.lead_dim;
-  return image_bytes(plan) + (size_t)graph_grid(P, D) * (size_t)slab_elems_of(D, LD, reg_mode(D)) * sizeof(Z);
+  return image_bytes(plan) + group_bytes(plan, P) +
+         (size_t)graph_grid(P, D) * (size_t)slab_elems_of(D, LD, reg_mode(D)) * sizeof(Z);
 }
 
 extern "C" int knit_graph_transmission(const knit_graph_plan *plan, const knit_graph_problem *probs, int32_t P,
@@ -970,7 +1232,31 @@ extern "C" int knit_graph_transmission(const knit_graph_plan *plan, const knit_g
   int32_t *img = reinterpret_cast<int32_t *>(ws);
   if (hipMemcpyAsync(img, plan->image.data(), plan->image.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return KNIT_E_DEVICE;
-  char *slabs = reinterpret_cast<char *>(ws) + image_bytes(plan);
+  char *next = reinterpret_cast<char *>(ws) + image_bytes(plan);
+  if (plan->block > 1) {   // gather the groups' blocks, then knit the groups
+    const int32_t *gmh = plan->gmap.data();
+    const size_t bb = (size_t)gmh[GM_MB] * gmh[GM_MB] * sizeof(knit_z);
+    int32_t *gm = reinterpret_cast<int32_t *>(next);
+    next += round256(plan->gmap.size() * 4);
+    knit_z *ghop = reinterpret_cast<knit_z *>(next);
+    next += round256((size_t)gmh[GM_NNZ] * bb);
+    knit_z *gons = reinterpret_cast<knit_z *>(next);
+    next += round256((size_t)P * gmh[GM_NC] * bb);
+    knit_graph_problem *gprobs = reinterpret_cast<knit_graph_problem *>(next);
+    next += round256((size_t)P * sizeof(knit_graph_problem));
+    if (hipMemcpyAsync(gm, gmh, plan->gmap.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) return KNIT_E_DEVICE;
+    const int64_t nh = (int64_t)gmh[GM_NNZ] * gmh[GM_MB] * gmh[GM_MB];
+    const int64_t no = (int64_t)P * gmh[GM_NC] * gmh[GM_MB] * gmh[GM_MB];
+    if (nh > 0)
+      hipLaunchKernelGGL(group_hop_kernel, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)), dim3(256), 0,
+                         s, gm, hop, ghop);
+    hipLaunchKernelGGL(group_onsite_kernel, dim3((unsigned)std::min<int64_t>((no + 255) / 256, 16384)), dim3(256),
+                       0, s, gm, probs, P, hop, onsite, gons, gprobs);
+    hop = ghop;
+    onsite = gons;
+    probs = gprobs;
+  }
+  char *slabs = next;
   const int D = plan->info.dim, LD = plan->info.lead_dim, grid = graph_grid(P, D);
   switch (plan->m) {
     case 1: launch_graph<1>(D, LD, grid, s, img, probs, P, hop, onsite, sigma, T, GLL, pstatus, slabs); break;

@@ -30,11 +30,12 @@ class KnitGraphLead(ctypes.Structure):
 class KnitGraphInfo(ctypes.Structure):
     _fields_ = [("nsite", c_i32), ("norb", c_i32), ("n_leads", c_i32), ("max_slots", c_i32), ("dim", c_i32),
                 ("lead_dim", c_i32), ("max_pairs", c_i32), ("n_steps", c_i32), ("sigma_size", c_i64),
-                ("nnz", c_i64), ("update_flops", c_dbl), ("update_bytes", c_dbl)]
+                ("nnz", c_i64), ("update_flops", c_dbl), ("update_bytes", c_dbl), ("block", c_i32),
+                ("reserved", c_i32)]
 
 
 assert ctypes.sizeof(KnitGraphLead) == 16
-assert ctypes.sizeof(KnitGraphInfo) == 64
+assert ctypes.sizeof(KnitGraphInfo) == 72
 
 GRAPH_PROBLEM_DTYPE = np.dtype([("E", "<f8"), ("onsite_off", "<i8"), ("sigma_off", "<i8"), ("gll_off", "<i8")])
 assert GRAPH_PROBLEM_DTYPE.itemsize == 32
@@ -42,6 +43,9 @@ assert GRAPH_PROBLEM_DTYPE.itemsize == 32
 _lib.knit_graph_plan_create.restype = c_i32
 _lib.knit_graph_plan_create.argtypes = [c_i32, c_i32, c_vp, c_vp, c_i32, ctypes.POINTER(KnitGraphLead), c_vp,
                                         ctypes.POINTER(c_vp)]
+_lib.knit_graph_plan_create_blocked.restype = c_i32
+_lib.knit_graph_plan_create_blocked.argtypes = [c_i32, c_i32, c_vp, c_vp, c_i32, ctypes.POINTER(KnitGraphLead), c_vp,
+                                                c_i32, ctypes.POINTER(c_vp)]
 _lib.knit_graph_plan_info.restype = c_i32
 _lib.knit_graph_plan_info.argtypes = [c_vp, ctypes.POINTER(KnitGraphInfo)]
 _lib.knit_graph_plan_order.restype = c_i32
@@ -53,7 +57,7 @@ _lib.knit_graph_workspace.argtypes = [c_vp, c_i32]
 _lib.knit_graph_transmission.restype = c_i32
 _lib.knit_graph_transmission.argtypes = [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
 
-EXPORTED = ["knit_graph_plan_create", "knit_graph_plan_info", "knit_graph_plan_order", "knit_graph_plan_destroy",
+EXPORTED = ["knit_graph_plan_create", "knit_graph_plan_create_blocked", "knit_graph_plan_info", "knit_graph_plan_order", "knit_graph_plan_destroy",
             "knit_graph_workspace", "knit_graph_transmission"]
 
 
@@ -62,7 +66,7 @@ class GraphPlan:
 
     _destroy = _lib.knit_graph_plan_destroy
 
-    def __init__(self, nsite: int, norb: int, row_ptr, col, leads, order=None):
+    def __init__(self, nsite: int, norb: int, row_ptr, col, leads, order=None, block: int | None = None):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.leads = [np.ascontiguousarray(l, dtype=np.int32) for l in leads]
@@ -75,9 +79,13 @@ class GraphPlan:
             ordp = self._order_in.ctypes.data
         h = c_vp()
         self.handle = None
-        code = _lib.knit_graph_plan_create(int(nsite), int(norb), self.row_ptr.ctypes.data,
-                                           self.col.ctypes.data if len(self.col) else None, len(self.leads), arr,
-                                           ordp, ctypes.byref(h))
+        colp = self.col.ctypes.data if len(self.col) else None
+        if block is None:   # site by site
+            code = _lib.knit_graph_plan_create(int(nsite), int(norb), self.row_ptr.ctypes.data, colp,
+                                               len(self.leads), arr, ordp, ctypes.byref(h))
+        else:               # `block` sites per step (0: automatic)
+            code = _lib.knit_graph_plan_create_blocked(int(nsite), int(norb), self.row_ptr.ctypes.data, colp,
+                                                       len(self.leads), arr, ordp, int(block), ctypes.byref(h))
         self.code = code
         if code == K.KNIT_OK:
             self.handle = h.value
@@ -105,9 +113,9 @@ class GraphPlan:
             self.handle = None
 
 
-def plan_create(nsite, norb, row_ptr, col, leads, order=None) -> GraphPlan:
-    p = GraphPlan(nsite, norb, row_ptr, col, leads, order)
-    K._check(p.code, "knit_graph_plan_create")
+def plan_create(nsite, norb, row_ptr, col, leads, order=None, block=None) -> GraphPlan:
+    p = GraphPlan(nsite, norb, row_ptr, col, leads, order, block)
+    K._check(p.code, "knit_graph_plan_create" if block is None else "knit_graph_plan_create_blocked")
     return p
 
 

@@ -288,10 +288,10 @@ class GraphBatch:
     packs (lead k's Sigma_k [n_k norb]^2 after the earlier leads').  Arranges arrays
     only; the knitting runs in ``knit_graph_transmission``."""
 
-    def __init__(self, g, leads, energies, onsites, sigmas, device="cuda", order=None):
+    def __init__(self, g, leads, energies, onsites, sigmas, device="cuda", order=None, block=None):
         from . import graph as GR
         self.g, self.leads = g, [np.asarray(l, dtype=np.int32) for l in leads]
-        self.plan = GR.plan_create(g.N, g.norb, g.row_ptr, g.col, self.leads, order)
+        self.plan = GR.plan_create(g.N, g.norb, g.row_ptr, g.col, self.leads, order, block)
         self.info = self.plan.info()
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
         P = len(E)

@@ -53,7 +53,7 @@ def test_library_exports_every_sampler_kernel_entry(K):
 
 
 def test_abi_version_and_status_strings(K):
-    assert K.abi_version() == 3
+    assert K.abi_version() == 4
     assert K.status_string(K.KNIT_E_ARG) == "invalid argument"
     assert "singular" in K.status_string(K.KNIT_P_SINGULAR)
 
@@ -342,7 +342,7 @@ def test_observable_entry_points_argument_checks(K):
 def test_library_exports_every_graph_entry(K):
     from paper_1010_2627_amd import graph as GR
     names = _declared("knit_graph.h")
-    assert len(names) == 6
+    assert len(names) == 7
     lib = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(lib, n), n
@@ -429,6 +429,62 @@ def test_graph_plan_rejects_bad_input(K):
     # norb out of range
     assert GR.GraphPlan(g.N, 0, rp, col, [left, right]).code == K.KNIT_E_ARG
     assert GR.GraphPlan(g.N, 5, rp, col, [left, right]).code == K.KNIT_E_ARG
+
+
+def test_blocked_graph_plan_of_a_rectangle(K):
+    """Groups of b sites: the leads' sites b at a time, the others b at a time in the site order.
+    The plan keeps the system's sizes (sites, orbitals, edges, lead block, self-energy pack) and
+    counts groups for the steps; block 1 is the site-by-site plan; automatic picks the largest
+    group that divides every lead and keeps the interface in registers."""
+    from paper_1010_2627_amd import graph as GR
+    Lx, W = 17, 8
+    g, left, right = _rect(Lx, W)
+    one = GR.plan_create(g.N, 1, g.row_ptr, g.col, [left, right])
+    i1 = one.info()
+    same = GR.plan_create(g.N, 1, g.row_ptr, g.col, [left, right], block=1).info()
+    assert same == i1 and i1["block"] == 1
+    for b in (2, 4):
+        p = GR.plan_create(g.N, 1, g.row_ptr, g.col, [left, right], block=b)
+        inf = p.info()
+        assert inf["block"] == b and inf["nsite"] == g.N and inf["norb"] == 1 and inf["nnz"] == i1["nnz"]
+        assert inf["lead_dim"] == i1["lead_dim"] and inf["sigma_size"] == i1["sigma_size"]
+        ngroups = -(-(g.N - 2 * W) // b) + 2 * W // b
+        assert inf["n_steps"] == ngroups - W // b
+        assert inf["dim"] % b == 0 and inf["dim"] >= i1["dim"] - 1
+        assert list(p.order()) == list(one.order())
+        # the groups' blocks take (P * groups + group edges) * b^2 elements more workspace
+        assert p.workspace(3) > one.workspace(3)
+    # automatic: site by site while the interface fits in registers (dimension <= 128) ...
+    auto = GR.plan_create(g.N, 1, g.row_ptr, g.col, [left, right], block=0)
+    assert auto.info()["block"] == 1 and auto.info() == i1
+    # ... above, groups of 3 sites where 3 divides the leads, else 4, else 2
+    gw, lw, rw = _rect(12, 81)
+    assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw]).info()["dim"] > 128
+    assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw], block=0).info()["block"] == 3
+    gw, lw, rw = _rect(12, 80)
+    assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw], block=0).info()["block"] == 4
+    gw, lw, rw = _rect(12, 82)
+    assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw], block=0).info()["block"] == 2
+    # two orbitals per site: groups of 2 sites (4 orbitals)
+    gb, lb, rb = _rect(12, 70, kind="bdg", mu=0.2, delta=0.1)
+    assert GR.plan_create(gb.N, 2, gb.row_ptr, gb.col, [lb, rb], block=0).info()["block"] == 2
+
+
+def test_blocked_graph_plan_rejects_bad_blocks(K):
+    from paper_1010_2627_amd import graph as GR
+    g, left, right = _rect(7, 6)
+    assert GR.GraphPlan(g.N, 1, g.row_ptr, g.col, [left, right], block=-1).code == K.KNIT_E_ARG
+    assert GR.GraphPlan(g.N, 1, g.row_ptr, g.col, [left, right], block=4).code == K.KNIT_E_ARG   # 4 does not divide 6
+    assert GR.GraphPlan(g.N, 1, g.row_ptr, g.col, [left, right], block=5).code == K.KNIT_E_ARG   # 5 orbitals per group
+    gb, lb, rb = _rect(6, 4, kind="bdg", mu=0.2, delta=0.1)
+    assert GR.GraphPlan(gb.N, 2, gb.row_ptr, gb.col, [lb, rb], block=4).code == K.KNIT_E_ARG     # 8 orbitals
+    # the site-by-site checks still come first
+    col3 = g.col.copy()
+    col3[0] = 0
+    assert GR.GraphPlan(g.N, 1, g.row_ptr, col3, [left, right], block=2).code == K.KNIT_E_ARG
+    # a lead whose sites do not divide: automatic falls back to site by site
+    g5, l5, r5 = _rect(6, 5)
+    assert GR.plan_create(g5.N, 1, g5.row_ptr, g5.col, [l5, r5], block=0).info()["block"] == 1
 
 
 def test_graph_plan_refuses_too_many_coupled_orbitals(K):

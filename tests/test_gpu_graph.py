@@ -46,14 +46,17 @@ def _oracle(g, leads, E, onsite, sigmas):
     return T, G[np.ix_(allidx, allidx)]
 
 
-def _check(g, leads, energies, onsites, sigmas, order=None, want_mode=None):
+def _check(g, leads, energies, onsites, sigmas, order=None, want_mode=None, block=None):
     from paper_1010_2627_amd import workload
-    b = workload.GraphBatch(g, leads, energies, onsites, sigmas, order=order)
+    b = workload.GraphBatch(g, leads, energies, onsites, sigmas, order=order, block=block)
+    if block is not None and block > 0:
+        assert b.info["block"] == block
     if want_mode is not None:
         D = b.info["dim"]
         mode = 0 if D <= 64 else (1 if D <= 128 else 2)
         assert mode == want_mode, (D, want_mode)
-    print(f"\ngraph N={g.N} norb={g.norb} leads={[len(l) for l in leads]} P={b.P} dim={b.info['dim']}", flush=True)
+    print(f"\ngraph N={g.N} norb={g.norb} leads={[len(l) for l in leads]} P={b.P} dim={b.info['dim']} "
+          f"block={b.info['block']}", flush=True)
     T, GLL, st = b.run(want_gll=True)
     torch.cuda.synchronize()
     T, GLL, st = T.cpu().numpy(), GLL.cpu().numpy(), st.cpu().numpy()
