@@ -367,6 +367,11 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
         if (tid < mm) shii[0][tid] = ldz(ons + (int64_t)srec[0][0] * mm + tid);
       }
       __syncthreads();
+      // Every load issued so far (the register matrix above all) completes
+      // here.  Otherwise the compiler, meeting those loads still in flight at
+      // the loop's entry, waits for all vector memory at the first staging
+      // store of every step, the three-steps-ahead prefetch included.
+      __builtin_amdgcn_s_waitcnt(0);
       for (int t = 0; t < nsteps; ++t) {
         const int cur = t & 1, nxt = cur ^ 1, rc = t & 3, rn = (t + 1) & 3;
         const int sl = srec[rc][1], Da = srec[rc][2], nent = srec[rc][3];
