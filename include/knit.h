@@ -110,6 +110,13 @@ enum {
  *   onsite_dense  0: each slice's on-site term D_n is given as W site blocks
  *                 [W][norb][norb]; 1: as a full [M][M] matrix (e.g. site-mixing
  *                 terms, or a basis rotation of a disordered strip)
+ *   h0_band  0, or b > 0: the caller's statement that the site blocks (a, c)
+ *            of H0 vanish for |a - c| > b (sites of a slice coupled only to
+ *            near neighbours within it, as on a lattice strip with hard
+ *            walls).  The matrix-core sweeps and the LDOS then read only that
+ *            band of H0 when they assemble a slice, which is the same sum
+ *            when the statement holds (the skipped entries are zeros).
+ *            Negative: KNIT_E_ARG.
  */
 typedef struct knit_strip {
   int32_t M;
@@ -119,7 +126,7 @@ typedef struct knit_strip {
   const knit_z *vblk;
   const knit_z *V;
   int32_t onsite_dense;
-  int32_t reserved;
+  int32_t h0_band;
 } knit_strip;
 
 /*

@@ -18,11 +18,12 @@ bool strip_ok(const knit_strip *s) {
   if (!s->H0) return false;
   if (!s->V && (!s->vcol || !s->vblk)) return false;
   if (s->onsite_dense != 0 && s->onsite_dense != 1) return false;
+  if (s->h0_band < 0) return false;
   return true;
 }
 
 StripDev strip_dev(const knit_strip &s) {
-  return StripDev{s.M, s.norb, s.H0, s.vcol, s.vblk, s.V, s.onsite_dense};
+  return StripDev{s.M, s.norb, s.H0, s.vcol, s.vblk, s.V, s.onsite_dense, s.h0_band};
 }
 
 // Dense couplings and dense on-site terms run on the matrix-core kernels only.

@@ -17,6 +17,7 @@ struct StripDev {
   const knit_z *vblk;
   const knit_z *V;        // dense [M][M] inter-slice hopping, or null (block-monomial vcol / vblk)
   int onsite_dense;       // on-site terms as [M][M] per slice instead of site blocks
+  int h0_band;            // 0, or the site-block half-bandwidth of H0 (blocks outside it are zero)
   // elements of one slice's on-site term in the on-site buffer
   __host__ __device__ int64_t onsite_stride() const {
     return onsite_dense ? (int64_t)M * M : (int64_t)M * norb;

@@ -887,6 +887,7 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
     const bool cpl = couple && real;
     const int ca = cpl ? s.vcol[sa] : -1, cb = cpl ? s.vcol[sb] : -1;
     const bool vgv = !first && ca >= 0 && cb >= 0;
+    const bool inband = s.h0_band == 0 || (sa > sb ? sa - sb : sb - sa) <= s.h0_band;
     cpx<double> gb[no][no];
     if (vgv)
 #pragma unroll
@@ -909,7 +910,8 @@ __device__ __forceinline__ void form_blocks_n(cpx<RG> *X, cpx<double> *A64, Stri
         cpx<double> out;
         if (real) {
           const int64_t e = (int64_t)(sa * no + oa) * M + sb * no + ob;
-          cpx<double> h = ld_z(s.H0 + e);
+          // H0 outside its stated band is zero: not read
+          cpx<double> h = inband ? ld_z(s.H0 + e) : cpx<double>{0.0, 0.0};
           if (s.onsite_dense || sa == sb) {
             const cpx<double> d = ld_z(D + (s.onsite_dense ? e : ((int64_t)sa * no + oa) * no + ob));
             h.re += d.re;

@@ -36,7 +36,7 @@ c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_doubl
 
 class KnitStrip(ctypes.Structure):
     _fields_ = [("M", c_i32), ("norb", c_i32), ("H0", c_vp), ("vcol", c_vp), ("vblk", c_vp), ("V", c_vp),
-                ("onsite_dense", c_i32), ("reserved", c_i32)]
+                ("onsite_dense", c_i32), ("h0_band", c_i32)]
 
 
 assert ctypes.sizeof(KnitStrip) == 48
@@ -221,6 +221,7 @@ class DeviceStrip:
     vblk: torch.Tensor | None    # [W, norb, norb] complex128 (block-monomial V)
     V: torch.Tensor | None = None   # [M, M] complex128 (dense V)
     onsite_dense: bool = False
+    h0_band: int = 0             # site-block half-bandwidth of H0 (0: read all of it)
 
     @classmethod
     def from_host(cls, strip, device="cuda"):
@@ -230,11 +231,21 @@ class DeviceStrip:
                    None if dense else t(strip.vcol, np.int32),
                    None if dense else t(strip.vblk),
                    t(strip.V) if dense else None,
-                   bool(getattr(strip, "onsite_dense", False)))
+                   bool(getattr(strip, "onsite_dense", False)), h0_band_of(strip.H0, strip.norb))
 
     def c(self) -> KnitStrip:
         return KnitStrip(self.M, self.norb, _ptr(self.H0), _ptr(self.vcol), _ptr(self.vblk), _ptr(self.V),
-                         int(self.onsite_dense), 0)
+                         int(self.onsite_dense), int(self.h0_band))
+
+
+def h0_band_of(H0, norb: int) -> int:
+    """Largest |a - c| over the nonzero site blocks (a, c) of a host H0, or 0 (read all of H0)
+    when that spans the slice anyway."""
+    W = H0.shape[0] // norb
+    nz = np.abs(np.asarray(H0).reshape(W, norb, W, norb)).max(axis=(1, 3)) != 0
+    a, c = np.nonzero(nz)
+    b = int(np.abs(a - c).max()) if len(a) else 0
+    return b if 0 < b < W - 1 else 0
 
 
 def strip_table(strips) -> ctypes.Array:

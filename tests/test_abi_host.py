@@ -90,7 +90,26 @@ def test_sweep_rejects_bad_strip_descriptions(K):
     assert _sweep(K, [_strip(M=4096)], good) == K.KNIT_E_ARG               # above KNIT_MAX_M
     assert _sweep(K, [_strip(H0=None)], good) == K.KNIT_E_ARG
     assert _sweep(K, [_strip(vcol=None)], good) == K.KNIT_E_ARG
+    bad_band = _strip()
+    bad_band.h0_band = -1
+    assert _sweep(K, [bad_band], good) == K.KNIT_E_ARG
     assert _sweep(K, [], good, n=0) == K.KNIT_E_ARG
+
+
+def test_h0_band_of_lattice_strips(K):
+    """Hard-wall lattice strips have site-block band 1 (nearest transverse neighbours); a band
+    that spans the slice, or no coupling at all, states nothing (0)."""
+    from paper_1010_2627_amd import inputs
+    sq = inputs.square_strip(12)
+    assert K.h0_band_of(sq.H0, sq.norb) == 1
+    ra = inputs.rashba_strip(8)
+    assert K.h0_band_of(ra.H0, ra.norb) == 1
+    W = 6
+    ring = np.zeros((W, W), dtype=np.complex128)
+    for a in range(W):
+        ring[a, (a + 1) % W] = ring[(a + 1) % W, a] = -1.0
+    assert K.h0_band_of(ring, 1) == 0        # periodic: the corner blocks span the slice
+    assert K.h0_band_of(np.eye(W, dtype=np.complex128), 1) == 0
 
 
 def test_sweep_rejects_bad_problems(K):
