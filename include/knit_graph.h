@@ -134,8 +134,9 @@ int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t *row_ptr, 
  * dim, max_pairs, n_steps, update_flops and update_bytes count groups, the
  * steps and the updates the device makes; block is the one chosen.
  * knit_graph_plan_order returns the site order the groups were taken from.
- * knit_graph_workspace grows by the groups' on-site blocks for every problem,
- * (P * n_groups + n_group_edges) * (block * norb)^2 knit_z.
+ * knit_graph_workspace grows by the groups' blocks, (P * n_groups +
+ * n_group_edges) * (block * norb)^2 knit_z (on-site blocks for every problem,
+ * hopping blocks once), plus the group map and a copy of the problem table.
  */
 int knit_graph_plan_create_blocked(int32_t nsite, int32_t norb, const int32_t *row_ptr, const int32_t *col,
                                    int32_t n_leads, const knit_graph_lead *leads, const int32_t *order,
