@@ -25,7 +25,7 @@ injected densities and site currents, the conductance matrix with a side lead
 (the last three on every strip cut to 64 slices except the eigenvalues), and
 the knitting of a system with a hole and three leads.
 
-Prints one JSON line. --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line. --gpus above 1 is refused: the benchmark runs on one GPU.
 """
 
 from __future__ import annotations
@@ -84,7 +84,7 @@ WORKLOADS = {
                desc="learned energy sampling on a zigzag ribbon (slice dim 200, L=1024, disorder U[-0.3,0.3]): "
                     "network trained by the library's BF16 kernels on 128 ribbons of the same width "
                     "(L in {64,128,256}, w in [0.2,0.8], targets from 1024 points per curve); 256 points vs 256 "
-                    "uniform on 8 held-out ribbons, judged by 4096 points"),
+                    "uniform on 8 held-out ribbons, measured against 4096 points"),
     "c3": dict(kind="uneven", n_strips=512, n_energies=32,
                desc="uneven batch in one persistent launch: 512 square-lattice strips, W ~ U{32,64,..,256}, "
                     "L ~ U[256,2048], disorder U[-w/2,w/2] with w ~ U[0.5,3], 32 midpoint energies in "
@@ -125,7 +125,7 @@ def open_channels(b):
 
 def sampler_bench(args, cfg):
     """Learned energy sampling at the ribbon size of the learned-sampling workload: train, then
-    place 256 points per held-out ribbon and judge the integrated conductance against the
+    place 256 points per held-out ribbon and measure the integrated conductance against the
     4096-point FP64 grid.  `value` is the transport throughput of the evaluation (T points/s)."""
     import torch
     from paper_1010_2627_amd import inputs, mlp, sampler as S
@@ -523,7 +523,7 @@ def main():
     if args.headline_only:
         args.no_mixed = args.no_ldos = args.no_cpu_baseline = args.no_observables = True
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (multi-GPU sharding "
                                    "is described, not run)"}))
         sys.exit(2)
 

@@ -62,7 +62,7 @@ enum {
   KNIT_E_ARG = -1,          /* invalid argument (nothing was enqueued) */
   KNIT_E_DEVICE = -2,       /* a HIP call failed */
   KNIT_E_WORKSPACE = -3,    /* ws is NULL or ws_bytes is below the *_workspace() size */
-  KNIT_E_UNSUPPORTED = -4,  /* valid request this build does not implement */
+  KNIT_E_UNSUPPORTED = -4,  /* valid request the library does not implement */
   KNIT_E_SCRATCH = -5       /* knit_rgf_sweep_noalloc: the request does not fit the
                                library's static scratch (nothing was enqueued) */
 };

@@ -111,7 +111,7 @@ const char *knit_status_string(int code) {
     case KNIT_E_ARG: return "invalid argument";
     case KNIT_E_DEVICE: return "HIP device error";
     case KNIT_E_WORKSPACE: return "workspace missing or too small";
-    case KNIT_E_UNSUPPORTED: return "not supported by this build";
+    case KNIT_E_UNSUPPORTED: return "not supported by this library";
     case KNIT_E_SCRATCH: return "request does not fit the library's static scratch";
     case KNIT_P_SINGULAR: return "singular slice";
     case KNIT_P_NOCONV: return "decimation not converged";

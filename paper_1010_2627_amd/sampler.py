@@ -25,7 +25,7 @@ every proposed point; nothing is interpolated from the network.
 5. **Integration.** The integrated conductance uses the trapezoid over the
    sorted 256 points, with the interval's end points (T evaluated there too).
 6. **Fallback.** A dense uniform grid is the fallback when p is not finite,
-   and a 4096-point one is the judge.
+   and a 4096-point one is the reference the error is measured against.
 
 **Training target.** A disordered ribbon's T(E) fluctuates on energy scales
 below the 256-point spacing, so the trapezoid error of each interval behaves
@@ -210,7 +210,7 @@ def place(p, n=N_LEARNED, mix=0.8):
                         for k, c in enumerate(cnt)])
     # the zigzag lead is singular at E = 0 (its flat edge band) and at E = +-t (every subband
     # meets there at the zone boundary), where its decimation does not converge: keep points
-    # at least 1e-3 away (the judge grid's nearest points are 7.3e-4 away)
+    # at least 1e-3 away (the 4096-point reference grid's nearest points are 7.3e-4 away)
     for e0 in (0.0, -1.0, 1.0):
         near = np.abs(E - e0) < 1e-3
         E[near] = np.where(E[near] < e0, e0 - 1e-3, e0 + 1e-3)
@@ -279,7 +279,7 @@ def train(net, X, Q, steps=300, batch=256, lr=2e-3, wd=1e-4, seed=0, device="cud
 
 def evaluate(net, ribbons, device="cuda", progress=None, chunk=16):
     """Integrated-conductance error of the learned 256 points and of 256 uniform points
-    against the 4096-point judge, per ribbon."""
+    against the 4096-point reference, per ribbon."""
     Ep, Eu, Ej = midpoints(N_PROBE), midpoints(N_TOTAL), midpoints(N_JUDGE)
     ends = np.array([EMIN, EMAX])
     nopen = open_channels([r.Nz for r in ribbons], midpoints(N_BINS), device)
@@ -295,11 +295,11 @@ def evaluate(net, ribbons, device="cuda", progress=None, chunk=16):
     for i in range(len(ribbons)):
         c = base[i]
         Te = c[n3:]
-        I_judge = integrate(np.concatenate([Ej, ends]), np.concatenate([c[n2:n3], Te]))
+        I_ref = integrate(np.concatenate([Ej, ends]), np.concatenate([c[n2:n3], Te]))
         I_uni = integrate(np.concatenate([Eu, ends]), np.concatenate([c[n1:n2], Te]))
         I_l = integrate(np.concatenate([Ep, pts[i], ends]), np.concatenate([T_probe[i], learned_T[i], Te]))
         I_t = integrate(np.concatenate([Ep, thr_pts[i], ends]), np.concatenate([T_probe[i], thr_T[i], Te]))
-        den = max(abs(I_judge), 1e-12)
-        rows.append({"err_uniform": abs(I_uni - I_judge) / den, "err_learned": abs(I_l - I_judge) / den,
-                     "err_threshold": abs(I_t - I_judge) / den, "fallback": bool(fb[i]), "I_judge": I_judge})
+        den = max(abs(I_ref), 1e-12)
+        rows.append({"err_uniform": abs(I_uni - I_ref) / den, "err_learned": abs(I_l - I_ref) / den,
+                     "err_threshold": abs(I_t - I_ref) / den, "fallback": bool(fb[i]), "I_ref": I_ref})
     return rows
