@@ -278,11 +278,20 @@ def graph_leg(steps=3):
     t = e0.elapsed_time(e1) / 1e3 / steps
     flops = inf["update_flops"] * P
     Tn = T.cpu().numpy()
+    # the automatic plan (groups of sites per step where they pay) beside it
+    ba = workload.GraphBatch(g, leads, E, inputs.graph_disorder(g, c["w"], seed=10102627), sig, block=0)
+    wsa = torch.empty(ba.plan.workspace(P), dtype=torch.uint8, device="cuda")
+    ta, (Ta, _, sta) = _timed_call(lambda: ba.run(ws=wsa), stream, steps)
+    auto = {"sites_per_step": ba.info["block"], "interface_dim_max": ba.info["dim"], "steps": ba.info["n_steps"],
+            "seconds_per_launch": round(ta, 5), "site_steps_per_s": inf["n_steps"] * P / ta,
+            "speedup": t / ta, "problems_with_status": int((sta.cpu().numpy() != 0).sum()),
+            "max_dT_vs_site_by_site": float(np.abs(Ta.cpu().numpy() - Tn).max())}
     return {"workload": c["desc"], "sites": inf["nsite"], "norb": inf["norb"], "leads": len(leads),
             "interface_dim_max": inf["dim"], "site_steps_per_launch": inf["n_steps"] * P,
             "seconds_per_launch": round(t, 5), "site_steps_per_s": inf["n_steps"] * P / t,
             "t_matrices_per_s": P / t, "problems_with_status": int((st.cpu().numpy() != 0).sum()),
             "row_sum_check_max": float(np.abs(Tn[:, 0, 1:].sum(axis=1) - Tn[:, 1:, 0].sum(axis=1)).max()),
+            "automatic_groups": auto,
             "roofline": {"bound": "alu", "achieved": flops / t / 1e12, "peak": PEAK_TFLOPS["fp64"],
                          "unit": "TFLOP/s", "frac": flops / t / 1e12 / PEAK_TFLOPS["fp64"],
                          "kernel": "graph_knit_kernel<512, 8, 4, true, 1> (interface matrix in registers)",

@@ -124,12 +124,14 @@ int knit_graph_plan_create(int32_t nsite, int32_t norb, const int32_t *row_ptr, 
  * latency over `block` sites.
  *   block   1 .. KNIT_MAX_NORB / norb, dividing every lead's nsite
  *           (KNIT_E_ARG otherwise); 1 gives knit_graph_plan_create's plan.
- *           0: automatic.  1 when the site-by-site interface dimension is
- *           at most 128 (the matrix stays in registers, where a step's cost
- *           grows with the orbitals it couples and groups gain nothing);
- *           above, where every step passes over the matrix in memory, the
- *           valid block with block * norb closest to 3 (the larger of two
- *           equally close) whose plan exists, else 1.
+ *           0: automatic.  When the site-by-site interface dimension is at
+ *           most 128 (the matrix stays in registers): 2 for one orbital per
+ *           site if 2 is valid and the grouped dimension stays within the
+ *           same register kernel (at most 64 when the site-by-site one is,
+ *           else at most 128), otherwise 1.  Above 128, where every step
+ *           passes over the matrix in memory: the valid block with
+ *           block * norb closest to 3 (the larger of two equally close)
+ *           whose plan exists, else 1.
  * info of a blocked plan: nsite, norb and nnz are the system's; max_slots,
  * dim, max_pairs, n_steps, update_flops and update_bytes count groups, the
  * steps and the updates the device makes; block is the one chosen.

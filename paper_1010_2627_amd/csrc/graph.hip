@@ -265,6 +265,9 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
   __shared__ int pcol[NPAIR];
   // register mode: step records and coupling blocks, double-buffered
   __shared__ int srec[4][REG ? 4 + 3 * NPAIR : 1], spcol[2][REG ? NPAIR : 1];
+  // register mode: own[t & 1][c] = (t << 5) | j when column (and row) c of the
+  // matrix is coupled orbital j of step t, written two steps ahead
+  __shared__ int own[2][REG ? DM : 1];
   __shared__ Z shr[2][REG ? NPAIR : 1][M], shc[2][REG ? NPAIR : 1][M], shii[2][M * M];
   __shared__ double sv[NT / WAVE];
   __shared__ int si[NT / WAVE];
@@ -356,7 +359,10 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
         const int tt = e / R;
         srec[tt][e % R] = tt < nsteps ? steps[(int64_t)tt * R + e % R] : 0;
       }
+      for (int e = tid; e < 2 * DM; e += NT) own[e / DM][e % DM] = -1;
       __syncthreads();
+      for (int tt = 0; tt < 2 && tt < nsteps; ++tt)
+        if (tid < srec[tt][3] * M) own[tt][srec[tt][4 + 3 * (tid / M)] * M + tid % M] = (tt << 5) | tid;
       if (nsteps > 0) {
         const int nent0 = srec[0][3];
         for (int e = tid; e < nent0 * mm; e += NT) {
@@ -388,21 +394,27 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
           phc = ldz(hop + (int64_t)srec[rn][6 + 3 * en] * mm + q * M + k);
         }
         if (has1 && tid < mm) phii = ldz(ons + (int64_t)srec[rn][0] * mm + tid);
-        // phase 1: the owners stage the coupled columns and rows; every register
-        // is addressed statically
+        // phase 1: the owners stage the coupled columns and rows, looked up in
+        // the ownership table (a fixed count of tests per thread, whatever the
+        // step couples); every register is addressed statically
         if (tid < np) spcol[cur][tid] = srec[rc][4 + 3 * (tid / M)] * M + tid % M;
-        for (int j = 0; j < np; ++j) {
-          const int cj = srec[rc][4 + 3 * (j / M)] * M + j % M;
 #pragma unroll
-          for (int b = 0; b < CPT; ++b)
-            if (tc + TC * b == cj)
+        for (int b = 0; b < CPT; ++b) {
+          const int v = own[cur][tc + TC * b];
+          if ((v >> 5) == t) {
+            const int j = v & 31;
 #pragma unroll
-              for (int a = 0; a < RPT; ++a) Gc[j][tr + 16 * a] = G.x[a][b];
+            for (int a = 0; a < RPT; ++a) Gc[j][tr + 16 * a] = G.x[a][b];
+          }
+        }
 #pragma unroll
-          for (int a = 0; a < RPT; ++a)
-            if (tr + 16 * a == cj)
+        for (int a = 0; a < RPT; ++a) {
+          const int v = own[cur][tr + 16 * a];
+          if ((v >> 5) == t) {
+            const int j = v & 31;
 #pragma unroll
-              for (int b = 0; b < CPT; ++b) Gr[j][tc + TC * b] = G.x[a][b];
+            for (int b = 0; b < CPT; ++b) Gr[j][tc + TC * b] = G.x[a][b];
+          }
         }
         __syncthreads();
         // every thread: g = (E - H_ii - H_{i,nb} G[nb, nb] H_{nb,i})^{-1} from the
@@ -498,6 +510,10 @@ __global__ __launch_bounds__(NT) void graph_knit_kernel(const int32_t *img, cons
         // the prefetched record and blocks (their slots are no longer read by any
         // thread: record t-1's slot, step t-1's blocks)
         if (has3 && tid < R) srec[(t + 3) & 3][tid] = recv;
+        if (t + 2 < nsteps) {   // ownership of step t+2 (its record arrived a step ago)
+          const int r2 = (t + 2) & 3;
+          if (tid < srec[r2][3] * M) own[cur][srec[r2][4 + 3 * (tid / M)] * M + tid % M] = ((t + 2) << 5) | tid;
+        }
         if (tid < nent1 * mm) {
           shr[nxt][tid / M][tid % M] = phr;
           shc[nxt][tid / M][tid % M] = phc;
@@ -1148,12 +1164,25 @@ extern "C" int knit_graph_plan_create_blocked(int32_t nsite, int32_t norb, const
     *plan = bp;
     return KNIT_OK;
   }
-  // Automatic.  With the interface in registers a step's cost grows with the
-  // orbitals it couples, so groups gain nothing there: site by site.  With the
-  // interface in the slab every step is a pass over it in memory, which groups
-  // share; the serial group inverse grows with the group, so groups of about
-  // three orbitals come first, then the larger of two equally close sizes.
+  // Automatic.  With the interface in registers a step has a fixed part that
+  // groups share and a part that grows with the square of the orbitals it
+  // couples (every thread forms the group's block): groups of two one-orbital
+  // sites, kept in the same register kernel (dimension up to 64, or up to
+  // 128), else site by site.  With the interface in the slab every step is a
+  // pass over it in memory, which groups share; the serial group inverse
+  // grows with the group, so groups of about three orbitals come first, then
+  // the larger of two equally close sizes.
   if (reg_mode(fine->info.dim)) {
+    if (norb == 1 && fits(2)) {
+      knit_graph_plan *bp = new (std::nothrow) knit_graph_plan();
+      const int lim = fine->info.dim <= 64 ? 64 : 128;
+      if (bp && build_blocked(*fine, row_ptr, col, n_leads, leads, 2, bp) == KNIT_OK && bp->info.dim <= lim) {
+        delete fine;
+        *plan = bp;
+        return KNIT_OK;
+      }
+      delete bp;
+    }
     *plan = fine;
     return KNIT_OK;
   }

@@ -473,9 +473,11 @@ def test_blocked_graph_plan_of_a_rectangle(K):
         assert list(p.order()) == list(one.order())
         # the groups' blocks take (P * groups + group edges) * b^2 elements more workspace
         assert p.workspace(3) > one.workspace(3)
-    # automatic: site by site while the interface fits in registers (dimension <= 128) ...
+    # automatic: groups of 2 one-orbital sites while the interface fits in registers ...
     auto = GR.plan_create(g.N, 1, g.row_ptr, g.col, [left, right], block=0)
-    assert auto.info()["block"] == 1 and auto.info() == i1
+    assert auto.info()["block"] == 2 and auto.info()["dim"] <= 64
+    g5, l5, r5 = _rect(17, 5)                      # 2 does not divide the leads: site by site
+    assert GR.plan_create(g5.N, 1, g5.row_ptr, g5.col, [l5, r5], block=0).info()["block"] == 1
     # ... above, groups of 3 sites where 3 divides the leads, else 4, else 2
     gw, lw, rw = _rect(12, 81)
     assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw]).info()["dim"] > 128
@@ -484,9 +486,12 @@ def test_blocked_graph_plan_of_a_rectangle(K):
     assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw], block=0).info()["block"] == 4
     gw, lw, rw = _rect(12, 82)
     assert GR.plan_create(gw.N, 1, gw.row_ptr, gw.col, [lw, rw], block=0).info()["block"] == 2
-    # two orbitals per site: groups of 2 sites (4 orbitals)
+    # two orbitals per site: groups of 2 sites (4 orbitals) with the interface in memory, site
+    # by site with it in registers
     gb, lb, rb = _rect(12, 70, kind="bdg", mu=0.2, delta=0.1)
     assert GR.plan_create(gb.N, 2, gb.row_ptr, gb.col, [lb, rb], block=0).info()["block"] == 2
+    gb, lb, rb = _rect(8, 6, kind="bdg", mu=0.2, delta=0.1)
+    assert GR.plan_create(gb.N, 2, gb.row_ptr, gb.col, [lb, rb], block=0).info()["block"] == 1
 
 
 def test_blocked_graph_plan_rejects_bad_blocks(K):
