@@ -511,6 +511,52 @@ def test_blocked_graph_plan_rejects_bad_blocks(K):
     assert GR.plan_create(g5.N, 1, g5.row_ptr, g5.col, [l5, r5], block=0).info()["block"] == 1
 
 
+def test_blocked_plans_of_random_graphs(K):
+    """Random connected graphs (degree <= 4), random leads and orders, every block size: the
+    plan is made or refused with an argument or support code, and a plan keeps the system's
+    sizes, counts steps of whole groups, and knits every site once."""
+    from paper_1010_2627_amd import graph as GR, inputs
+    for seed in range(12):
+        rng = np.random.Generator(np.random.PCG64(900 + seed))
+        N, m = int(rng.integers(20, 60)), int(rng.integers(1, 3))
+        perm = rng.permutation(N)
+        bonds = {(int(a), int(b)): np.eye(m) for a, b in zip(perm[:-1], perm[1:])}
+        deg = np.bincount(np.array(list(bonds)).ravel(), minlength=N)
+        for _ in range(N // 3):
+            a, b = (int(x) for x in rng.integers(0, N, 2))
+            if a != b and deg[a] < 4 and deg[b] < 4 and (a, b) not in bonds and (b, a) not in bonds:
+                bonds[(a, b)] = np.eye(m)
+                deg[a] += 1
+                deg[b] += 1
+        g = inputs.graph_from_blocks(N, m, np.zeros((N, m, m)), bonds)
+        sizes = [int(x) for x in rng.choice([2, 4, 6], size=int(rng.integers(1, 4)))]
+        pick = rng.permutation(N)
+        leads, o = [], 0
+        for s in sizes:
+            leads.append([int(x) for x in pick[o:o + s]])
+            o += s
+        order = rng.permutation(N) if seed % 2 else None
+        ref = GR.GraphPlan(N, m, g.row_ptr, g.col, leads, order)
+        assert ref.ok(), (seed, ref.code)
+        r = ref.info()
+        for block in (0, 1, 2, 3, 4):
+            p = GR.GraphPlan(N, m, g.row_ptr, g.col, leads, order, block=block)
+            if not p.ok():
+                assert p.code in (K.KNIT_E_ARG, K.KNIT_E_UNSUPPORTED), (seed, block, p.code)
+                assert block >= 2
+                continue
+            inf = p.info()
+            b = inf["block"]
+            assert b == block or block == 0, (seed, block, b)
+            assert inf["nsite"] == N and inf["norb"] == m and inf["nnz"] == r["nnz"]
+            assert inf["lead_dim"] == r["lead_dim"] and inf["sigma_size"] == r["sigma_size"]
+            assert inf["dim"] % (b * m) == 0 and inf["max_pairs"] <= 16
+            groups = sum(len(l) // b for l in leads) + -(-(N - sum(sizes)) // b)
+            assert inf["n_steps"] == groups - len(leads[0]) // b
+            assert sorted(p.order()) == list(range(N))
+            assert p.workspace(5) >= ref.workspace(5) or b == 1
+
+
 def test_graph_plan_refuses_too_many_coupled_orbitals(K):
     """A site joining 5 earlier neighbours with 4 orbitals each couples 20 > 16 orbitals."""
     from paper_1010_2627_amd import graph as GR, inputs

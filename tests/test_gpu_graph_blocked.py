@@ -5,7 +5,8 @@ included) against the oracle's dense inverse.
 Cases: groups of 2, 3 and 4 sites with one orbital, groups of 2 sites with two
 orbitals (electron-hole blocks), a last group padded with decoupled orbitals,
 three and four leads with flux and a hole, the interface in registers and in
-the workgroup's slab, and the automatic choice (groups of 3 in slab mode).  T_kl and the lead block of G
+the workgroup's slab, random graphs with one and two orbitals per site, and
+the automatic choice (groups of 3 in slab mode).  T_kl and the lead block of G
 agree with the oracle at 1e-10 relative to max(1, |x|), as site by site.
 """
 
@@ -88,3 +89,15 @@ def test_automatic_groups_of_three_in_slab_mode():
     P = 3
     T, _ = _check(g, leads, [-1.1, 0.4, 2.2], inputs.graph_disorder(g, 1.0, seed=13), _synthetic(leads, 1, P, 600),
                   want_mode=2, block=0)
+
+
+@gpu
+@pytest.mark.parametrize("m", [1, 2])
+def test_blocked_random_graph(m):
+    """A random connected graph with random hopping and on-site blocks, three leads of even
+    size, groups of 2 sites (2 or 4 orbitals per group)."""
+    from test_gpu_graph import _random_graph
+    g, perm = _random_graph(40, m, seed=10 + m)
+    leads = [[int(x) for x in perm[:4]], [int(x) for x in perm[-4:]], [int(x) for x in perm[18:20]]]
+    P = 3
+    _check(g, leads, [-0.5, 0.2, 1.1], g.onsite, _synthetic(leads, m, P, 700 + m), block=2)
